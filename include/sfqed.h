@@ -1,0 +1,217 @@
+/* sfqed.h -- C ABI of libsfqed, the MI355X (gfx950) per-macroparticle
+ * strong-field QED event generator.
+ *
+ * The library implements the inverse-sampling generator with sub-cycling of
+ * arXiv:2409.17299 (Sec. 3, Algorithms 1 and 2): for every electron, positron
+ * and photon it evaluates the quantum parameter chi, the locally-constant-field
+ * emission or pair rate from precomputed tables, carries an FP64 optical depth
+ * across sub-cycles, samples the energy fraction of each new particle by
+ * inverse CDF, applies collinear recoil and appends the new photons and pairs
+ * in a deterministic order.  New particles are advanced to the end of the same
+ * global step (Algorithm 2).
+ *
+ * Units throughout: momenta in m_e c; E in E_S = m_e^2 c^3/(e hbar); B in
+ * E_S / c; times in hbar/(m_e c^2); lengths in hbar/(m_e c).
+ *
+ * Memory: every particle and field array is a device pointer owned by the
+ * caller (for example torch tensors); tables and surrogate networks are owned
+ * by the library.  All calls are ordered on the HIP stream passed as
+ * `stream` (NULL = the null stream).  qed_step synchronises that stream once
+ * per generation round to read the append counters; no other call blocks.
+ *
+ * Errors: every function returns a qed_status and never aborts.  Invalid
+ * arguments are rejected before any work is queued.
+ */
+#ifndef SFQED_H
+#define SFQED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QED_OK = 0,
+  QED_ERR_ARG = 1,       /* bad pointer, size, dtype or configuration */
+  QED_ERR_CAPACITY = 2,  /* an append or merge target is too small; see qed_step_stats */
+  QED_ERR_HIP = 3,       /* a HIP runtime call failed */
+  QED_ERR_STATE = 4,     /* object not built / wrong object kind */
+  QED_ERR_EVENT_CAP = 5  /* a particle reached max_events in one step */
+} qed_status;
+
+typedef enum { QED_F32 = 0, QED_F64 = 1 } qed_dtype;
+typedef enum { QED_SAMPLER_TABLE = 0, QED_SAMPLER_MLP = 1 } qed_sampler;
+enum { QED_ELECTRON = 0, QED_POSITRON = 1, QED_PHOTON = 2 };
+enum { QED_EMISSION = 0, QED_PAIR = 1 };
+
+/* ------------------------------------------------------------------ tables
+ * Rates (Sec. 3: one rate evaluation per event or per global step) and
+ * inverse CDFs (Sec. 3: two-dimensional look-up tables in energy fraction and
+ * chi) of nonlinear Compton emission and Breit-Wheeler pair production in the
+ * locally-constant-field approximation, built on the GPU in FP64 by quadrature
+ * of the modified-Bessel spectra.
+ *  - FP64 rates: piecewise Chebyshev (degree 16, segments of 0.5 in ln chi)
+ *    of g(s) = ln(W gamma / (alpha chi)) (emission) and
+ *    ln(W eps/(alpha chi)) + 8/(3 chi) (pairs) over [rate_chi_min, rate_chi_max].
+ *  - FP32 rates: cubic Hermite of the same g on rate_nodes uniform nodes.
+ *  - Inverse CDFs: q = logit(delta) - ln chi (emission) and q = logit(xi)
+ *    (pairs, xi <= 1/2 tabulated, the rest by symmetry) on a uniform grid in
+ *    (ln chi, logit r); FP32 grids are staged in LDS by the step kernels, FP64
+ *    grids are f64_refine times finer in both directions and stay in HBM.
+ */
+typedef struct {
+  double rate_chi_min, rate_chi_max; /* FP64 Chebyshev and FP32 Hermite range */
+  int32_t rate_nodes;                /* FP32 Hermite nodes */
+  double rad_chi_min, rad_chi_max;   /* emission inverse-CDF chi range */
+  int32_t rad_rows, rad_cols;        /* FP32 emission grid (ln chi x logit r) */
+  double rad_x_min, rad_x_max;       /* logit r range of the emission grid */
+  double pair_chi_min, pair_chi_max; /* pair inverse-CDF chi range */
+  int32_t pair_rows, pair_cols;      /* FP32 pair grid; logit r in [pair_x_min, 0] */
+  double pair_x_min;
+  int32_t f64_refine;                /* FP64 grids: (rows-1)*k+1 x (cols-1)*k+1 */
+} qed_table_cfg;
+
+typedef struct qed_tables qed_tables; /* opaque, library-owned device memory */
+
+/* Fills cfg with the defaults (rates on [1e-7, 1e5], emission CDF on
+ * [1e-4, 1e4] x [-10, 23] with 72 x 265 nodes, pair CDF on [1e-2, 1e4] x
+ * [-23, 0] with 47 x 185 nodes, FP64 refinement 4). */
+void qed_table_cfg_default(qed_table_cfg *cfg);
+
+/* Builds all tables on the device of the current HIP context, ordered on
+ * `stream`; *out receives the handle.  Returns QED_ERR_ARG for an invalid
+ * cfg (ranges must be positive and increasing, grids >= 4 nodes, the FP32
+ * emission grid must fit in 96 KiB of LDS). */
+qed_status qed_build_rate_tables(const qed_table_cfg *cfg, void *stream, qed_tables **out);
+void qed_tables_free(qed_tables *t);
+
+/* Table export for validation.  which: 0 emission Chebyshev coefficients,
+ * 1 pair Chebyshev coefficients (double [segments][17]), 2 emission FP32
+ * Hermite (float [nodes][2]: g, h g'), 3 pair FP32 Hermite, 4 emission FP32
+ * inverse CDF (float [rows][cols]), 5 pair FP32 inverse CDF, 6 emission FP64
+ * inverse CDF (double), 7 pair FP64 inverse CDF.  *bytes receives the size
+ * when dst is NULL; otherwise exactly that many bytes are copied (blocking). */
+qed_status qed_tables_export(const qed_tables *t, int which, void *dst, size_t *bytes);
+
+/* ------------------------------------------------------------------ particles
+ * One species, structure of arrays, caller-owned device pointers.  Momenta and
+ * positions have the step's dtype.  x, y, z may all be NULL (positions not
+ * advanced).  alive is required for photons (a photon that produced a pair is
+ * marked 0) and ignored for leptons.  nev (optional) receives the number of
+ * events of each processed particle in the last step.  root and t_birth are
+ * used only in append buffers: root = species << 30 | index of the particle of
+ * the input ensemble whose fields the particle sees; t_birth (dtype) is the
+ * time within the step at which it was created. */
+typedef struct {
+  void *px, *py, *pz;
+  void *x, *y, *z;
+  float *w;
+  double *tau;
+  uint64_t *id;
+  uint8_t *alive;
+  int32_t *nev;
+  uint32_t *root;
+  void *t_birth;
+  int64_t count, capacity;
+} qed_species;
+
+/* Per-particle fields of one species (dtype of the step), indexed like the
+ * particles when stride = 1, or one shared value when stride = 0. */
+typedef struct {
+  const void *ex, *ey, *ez, *bx, *by, *bz;
+  int64_t stride;
+} qed_fields;
+
+typedef struct {
+  qed_dtype dtype;
+  qed_species s[3]; /* QED_ELECTRON, QED_POSITRON, QED_PHOTON */
+  qed_fields f[3];
+} qed_ensemble;
+
+typedef struct {
+  int32_t emission, pair, push; /* processes on/off; push: Boris between events */
+  qed_sampler sampler;          /* QED_SAMPLER_MLP uses `mlp` inside its trained range */
+  const void *mlp;
+  double gamma_min;             /* leptons with gamma < gamma_min do not emit (>= 1) */
+  int64_t max_events;           /* per particle and step; reaching it is an error */
+  int32_t profile;              /* 1: time every launch with HIP events into stats */
+} qed_step_cfg;
+
+void qed_step_cfg_default(qed_step_cfg *cfg);
+
+typedef struct {
+  int64_t n_emit, n_pair;           /* events of the step */
+  int64_t n_new[3];                 /* particles appended per species */
+  int64_t n_rounds;                 /* generation rounds (Algorithm 2 loop trips) */
+  int64_t max_events;               /* largest number of events of one particle */
+  int64_t required_capacity[3];     /* append sizes needed (lower bound on overflow) */
+  int64_t n_launches;               /* particle-range launches (count, scan, write each) */
+  double ms_lepton, ms_photon;      /* summed kernel time of lepton / photon launches (profile = 1) */
+  double ms_lepton_main;            /* the lepton launches over the input ensemble */
+  double ms_count_main;             /* ... their count kernels only */
+  double ms_write_main;             /* ... their scan + write kernels */
+  int64_t n_lepton_main;            /* particles in those launches */
+  int64_t n_children_main;          /* photons they appended */
+} qed_step_stats;
+
+/* Draws tau = -ln(u) for every particle with tau < 0 (u from Philox4x32-10,
+ * key = seed, counter = (id_lo, id_hi, step, 0xFFFFFFFF)). */
+qed_status qed_init_tau(qed_ensemble *ens, uint64_t seed, uint32_t step, void *stream);
+
+/* One global step of length dt (Algorithms 1 and 2).  Every particle of `ens`
+ * is advanced from t = 0 to dt; new particles are appended to `app` (counts
+ * start from zero) and advanced from their birth time to dt in later rounds.
+ * Momenta, positions, tau and nev of `ens` and `app` are updated in place;
+ * photons that produced a pair get alive = 0.  Random draws: Philox4x32-10,
+ * key = seed, counter = (id_lo, id_hi, step, j) for the j-th event of a
+ * particle in the step; the ids of new particles come from counter word
+ * j | 0x80000000.  Order of `app`: creation rounds in order; within a round
+ * electrons, then positrons, then photons are processed in index order and
+ * each one's children are appended in event order.
+ * On QED_ERR_CAPACITY nothing is written past any capacity and
+ * stats->required_capacity tells how much would have been needed; the
+ * ensemble is then partly advanced and the caller restores it. */
+qed_status qed_step(const qed_tables *tab, const qed_step_cfg *cfg, qed_ensemble *ens, qed_species app[3],
+                    double dt, uint64_t seed, uint32_t step, qed_step_stats *stats, void *stream);
+
+/* Merge (the merge of per-thread arrays of Sec. 4.2): drops photons with
+ * alive = 0 from `ens` (stable), then appends the surviving particles of
+ * `app` after each species.  Capacity of ens->s[k] must hold the result,
+ * otherwise QED_ERR_CAPACITY and nothing is changed.  ens->s[k].count is
+ * updated (blocking: one small device-to-host copy). */
+qed_status qed_merge(qed_ensemble *ens, const qed_species app[3], void *stream);
+
+/* ------------------------------------------------------------------ kernels of the step, exposed for validation
+ * Rates W (per unit time) of one process for given chi and energy (gamma for
+ * emission, eps for pairs), evaluated exactly as inside qed_step (FP64:
+ * Chebyshev; FP32: Hermite), in dtype.  Pairs below eps = 2 are not masked
+ * here (qed_eval_particles does). */
+qed_status qed_eval_rate(const qed_tables *t, int process, qed_dtype dtype, const void *chi, const void *energy,
+                         void *w_out, int64_t n, void *stream);
+
+/* chi and rate of each particle of one species (dtype arrays, fields with stride). */
+qed_status qed_eval_particles(const qed_tables *t, int species, qed_dtype dtype, const void *px, const void *py,
+                              const void *pz, const qed_fields *f, int64_t n, void *chi_out, void *w_out,
+                              void *stream);
+
+/* Inverse-CDF samples: out = delta (emission) or xi (pairs) for chi and raw
+ * 32-bit uniforms k (r = (k + 1/2) / 2^32). */
+qed_status qed_sample(const qed_tables *t, int process, qed_dtype dtype, const void *chi, const uint32_t *k,
+                      void *out, int64_t n, void *stream);
+
+/* Grid geometry of built tables (21 doubles): nseg_rad, s_lo_rad, nseg_pair,
+ * s_lo_pair, hermite_nodes, then per process (emission, pairs): rows32,
+ * cols32, rows64, cols64, s_first, s_last, x_first, x_last. */
+qed_status qed_tables_geometry(const qed_tables *t, double *out, int n);
+
+const char *qed_status_str(qed_status s);
+/* Message of the last failure on the calling thread (empty if none). */
+const char *qed_last_error(void);
+int32_t qed_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFQED_H */

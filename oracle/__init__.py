@@ -205,17 +205,26 @@ def sample_pair(chi, k) -> tuple[np.ndarray, np.ndarray]:
     return d, o
 
 
-def sample_rad_r(chi: float, r: float, definition: bool = False) -> float:
+def sample_rad_r(chi: float, r: float, definition: bool = False, rc: float | None = None) -> float:
+    """delta at uniform r (rc = 1 - r, pass it when r is close to 1)."""
     d = C.c_double()
     o = C.c_double()
-    lib().orc_sample_rad_r(chi, r, 1.0 - r, int(definition), C.byref(d), C.byref(o))
+    lib().orc_sample_rad_r(chi, r, 1.0 - r if rc is None else rc, int(definition), C.byref(d), C.byref(o))
     return d.value
 
 
-def sample_pair_r(chi: float, r: float, definition: bool = False) -> float:
+def sample_rad_r2(chi: float, r: float, rc: float) -> tuple[float, float]:
+    """delta and 1 - delta."""
     d = C.c_double()
     o = C.c_double()
-    lib().orc_sample_pair_r(chi, r, 1.0 - r, int(definition), C.byref(d), C.byref(o))
+    lib().orc_sample_rad_r(chi, r, rc, 0, C.byref(d), C.byref(o))
+    return d.value, o.value
+
+
+def sample_pair_r(chi: float, r: float, definition: bool = False, rc: float | None = None) -> float:
+    d = C.c_double()
+    o = C.c_double()
+    lib().orc_sample_pair_r(chi, r, 1.0 - r if rc is None else rc, int(definition), C.byref(d), C.byref(o))
     return d.value
 
 

@@ -1,0 +1,385 @@
+"""MI355X (gfx950) per-macroparticle strong-field QED event generator.
+
+Python binding of libsfqed (``include/sfqed.h``): argument marshalling only.
+Every step of the generator runs in the library's HIP kernels; PyTorch provides
+device memory and the stream.  Importing works without a GPU; the first call
+that needs the library raises ``SfqedError`` if ``libsfqed.so`` was not built
+(``python -m paper_2409_17299_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libsfqed.so"
+
+ELECTRON, POSITRON, PHOTON = 0, 1, 2
+EMISSION, PAIR = 0, 1
+F32, F64 = 0, 1
+STATUS = {0: "ok", 1: "invalid argument", 2: "capacity exceeded", 3: "HIP runtime error", 4: "invalid state",
+          5: "max_events reached"}
+
+
+class SfqedError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+# ----------------------------------------------------------------------------- C structs
+class TableCfg(C.Structure):
+    _fields_ = [("rate_chi_min", C.c_double), ("rate_chi_max", C.c_double), ("rate_nodes", C.c_int32),
+                ("rad_chi_min", C.c_double), ("rad_chi_max", C.c_double), ("rad_rows", C.c_int32),
+                ("rad_cols", C.c_int32), ("rad_x_min", C.c_double), ("rad_x_max", C.c_double),
+                ("pair_chi_min", C.c_double), ("pair_chi_max", C.c_double), ("pair_rows", C.c_int32),
+                ("pair_cols", C.c_int32), ("pair_x_min", C.c_double), ("f64_refine", C.c_int32)]
+
+
+class CSpecies(C.Structure):
+    _fields_ = [("px", C.c_void_p), ("py", C.c_void_p), ("pz", C.c_void_p), ("x", C.c_void_p),
+                ("y", C.c_void_p), ("z", C.c_void_p), ("w", C.c_void_p), ("tau", C.c_void_p),
+                ("id", C.c_void_p), ("alive", C.c_void_p), ("nev", C.c_void_p), ("root", C.c_void_p),
+                ("t_birth", C.c_void_p), ("count", C.c_int64), ("capacity", C.c_int64)]
+
+
+class CFields(C.Structure):
+    _fields_ = [("ex", C.c_void_p), ("ey", C.c_void_p), ("ez", C.c_void_p), ("bx", C.c_void_p),
+                ("by", C.c_void_p), ("bz", C.c_void_p), ("stride", C.c_int64)]
+
+
+class CEnsemble(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("s", CSpecies * 3), ("f", CFields * 3)]
+
+
+class StepCfg(C.Structure):
+    _fields_ = [("emission", C.c_int32), ("pair", C.c_int32), ("push", C.c_int32), ("sampler", C.c_int),
+                ("mlp", C.c_void_p), ("gamma_min", C.c_double), ("max_events", C.c_int64),
+                ("profile", C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("n_emit", C.c_int64), ("n_pair", C.c_int64), ("n_new", C.c_int64 * 3), ("n_rounds", C.c_int64),
+                ("max_events", C.c_int64), ("required_capacity", C.c_int64 * 3), ("n_launches", C.c_int64),
+                ("ms_lepton", C.c_double), ("ms_photon", C.c_double), ("ms_lepton_main", C.c_double),
+                ("ms_count_main", C.c_double), ("ms_write_main", C.c_double), ("n_lepton_main", C.c_int64),
+                ("n_children_main", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if hasattr(v, "__len__") else v
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libsfqed (raises SfqedError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise SfqedError(4, f"{LIB_PATH} is missing: build it with python -m paper_2409_17299_amd.build")
+        L = C.CDLL(str(LIB_PATH))
+        v, p, i64 = C.c_void_p, C.c_void_p, C.c_int64
+        sig = {
+            "qed_table_cfg_default": (None, [C.POINTER(TableCfg)]),
+            "qed_build_rate_tables": (C.c_int, [C.POINTER(TableCfg), v, C.POINTER(v)]),
+            "qed_tables_free": (None, [v]),
+            "qed_tables_export": (C.c_int, [v, C.c_int, v, C.POINTER(C.c_size_t)]),
+            "qed_tables_geometry": (C.c_int, [v, C.POINTER(C.c_double), C.c_int]),
+            "qed_step_cfg_default": (None, [C.POINTER(StepCfg)]),
+            "qed_init_tau": (C.c_int, [C.POINTER(CEnsemble), C.c_uint64, C.c_uint32, v]),
+            "qed_step": (C.c_int, [v, C.POINTER(StepCfg), C.POINTER(CEnsemble), C.POINTER(CSpecies), C.c_double,
+                                   C.c_uint64, C.c_uint32, C.POINTER(StepStats), v]),
+            "qed_merge": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CSpecies), v]),
+            "qed_eval_rate": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
+            "qed_eval_particles": (C.c_int, [v, C.c_int, C.c_int, p, p, p, C.POINTER(CFields), i64, p, p, v]),
+            "qed_sample": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
+            "qed_status_str": (C.c_char_p, [C.c_int]),
+            "qed_last_error": (C.c_char_p, []),
+            "qed_abi_version": (C.c_int32, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise SfqedError(rc, lib().qed_last_error().decode(errors="replace"))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------------------- tables
+def default_table_cfg(**overrides) -> TableCfg:
+    cfg = TableCfg()
+    lib().qed_table_cfg_default(C.byref(cfg))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+TABLE_PARTS = {"cheb_rad": 0, "cheb_pair": 1, "herm_rad": 2, "herm_pair": 3, "cdf32_rad": 4, "cdf32_pair": 5,
+               "cdf64_rad": 6, "cdf64_pair": 7}
+
+
+class Tables:
+    """Rate and inverse-CDF tables built on the current device (blocking)."""
+
+    def __init__(self, cfg: TableCfg | None = None, stream=None):
+        self.cfg = cfg if cfg is not None else default_table_cfg()
+        h = C.c_void_p()
+        _check(lib().qed_build_rate_tables(C.byref(self.cfg), _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.qed_tables_free(h)
+            self.handle = None
+
+    def export(self, part: str) -> np.ndarray:
+        which = TABLE_PARTS[part]
+        n = C.c_size_t(0)
+        _check(lib().qed_tables_export(self.handle, which, None, C.byref(n)))
+        dt = np.float64 if which in (0, 1, 6, 7) else np.float32
+        out = np.empty(n.value // np.dtype(dt).itemsize, dtype=dt)
+        _check(lib().qed_tables_export(self.handle, which, out.ctypes.data_as(C.c_void_p), C.byref(n)))
+        g = self.geometry()
+        if which in (0, 1):
+            return out.reshape(-1, 17)
+        if which in (2, 3):
+            return out.reshape(-1, 2)
+        p = which % 2
+        rows, cols = (g[f"rows32_{p}"], g[f"cols32_{p}"]) if which in (4, 5) else (g[f"rows64_{p}"], g[f"cols64_{p}"])
+        return out.reshape(rows, cols)
+
+    def geometry(self) -> dict:
+        v = (C.c_double * 21)()
+        _check(lib().qed_tables_geometry(self.handle, v, 21))
+        names = ["nseg_0", "s_lo_0", "nseg_1", "s_lo_1", "herm_n"]
+        for p in (0, 1):
+            names += [f"rows32_{p}", f"cols32_{p}", f"rows64_{p}", f"cols64_{p}", f"s0_{p}", f"s1_{p}", f"x0_{p}",
+                      f"x1_{p}"]
+        return {k: (int(x) if k.startswith(("nseg", "herm", "rows", "cols")) else float(x)) for k, x in zip(names, v)}
+
+
+# ----------------------------------------------------------------------------- particle stores
+@dataclass
+class Store:
+    """One species in device memory (structure of arrays, torch tensors)."""
+    px: object
+    py: object
+    pz: object
+    w: object
+    tau: object
+    id: object
+    alive: object = None
+    nev: object = None
+    root: object = None
+    t_birth: object = None
+    x: object = None
+    y: object = None
+    z: object = None
+    count: int = 0
+    cap: int | None = None  # capacity passed to the library (default: the tensor length)
+
+    @property
+    def capacity(self) -> int:
+        return int(self.px.numel()) if self.cap is None else int(self.cap)
+
+    @property
+    def dtype(self):
+        return self.px.dtype
+
+    @classmethod
+    def empty(cls, capacity: int, dtype=None, photon: bool = False, append: bool = False, positions: bool = False,
+              nev: bool = True, device="cuda"):
+        torch = _torch()
+        dtype = dtype or torch.float32
+        cap = max(int(capacity), 0)
+        z = lambda dt: torch.zeros(cap, dtype=dt, device=device)  # noqa: E731
+        s = cls(z(dtype), z(dtype), z(dtype), z(torch.float32), z(torch.float64), z(torch.int64))
+        if photon:
+            s.alive = torch.ones(cap, dtype=torch.uint8, device=device)
+        if nev:
+            s.nev = z(torch.int32)
+        if append:
+            s.root = z(torch.int32)
+            s.t_birth = z(dtype)
+        if positions:
+            s.x, s.y, s.z = z(dtype), z(dtype), z(dtype)
+        return s
+
+    @classmethod
+    def from_arrays(cls, p, w, tau, ids, dtype=None, capacity=None, photon=False, positions=None, x=None,
+                    device="cuda"):
+        torch = _torch()
+        dtype = dtype or torch.float32
+        n = len(ids)
+        s = cls.empty(capacity if capacity is not None else n, dtype, photon=photon, positions=x is not None,
+                      device=device)
+        p = torch.as_tensor(np.asarray(p, dtype=np.float64))
+        s.px[:n] = p[:, 0].to(dtype)
+        s.py[:n] = p[:, 1].to(dtype)
+        s.pz[:n] = p[:, 2].to(dtype)
+        s.w[:n] = torch.as_tensor(np.asarray(w, dtype=np.float32))
+        s.tau[:n] = torch.as_tensor(np.asarray(tau, dtype=np.float64))
+        s.id[:n] = torch.as_tensor(np.asarray(ids, dtype=np.uint64).view(np.int64))
+        if x is not None:
+            xx = torch.as_tensor(np.asarray(x, dtype=np.float64))
+            s.x[:n], s.y[:n], s.z[:n] = xx[:, 0].to(dtype), xx[:, 1].to(dtype), xx[:, 2].to(dtype)
+        s.count = n
+        return s
+
+    def c(self) -> CSpecies:
+        return CSpecies(*[_ptr(t) for t in (self.px, self.py, self.pz, self.x, self.y, self.z, self.w, self.tau,
+                                            self.id, self.alive, self.nev, self.root, self.t_birth)],
+                        self.count, self.capacity)
+
+    def host(self) -> dict:
+        """Live part copied to host numpy arrays (momenta as [n, 3] float64)."""
+        n = self.count
+        out = {"p": np.stack([t[:n].double().cpu().numpy() for t in (self.px, self.py, self.pz)], axis=1),
+               "w": self.w[:n].cpu().numpy(), "tau": self.tau[:n].cpu().numpy(),
+               "id": self.id[:n].cpu().numpy().view(np.uint64)}
+        for name in ("alive", "nev", "root", "t_birth"):
+            t = getattr(self, name)
+            if t is not None:
+                a = t[:n].cpu().numpy()
+                out[name] = a.view(np.uint32) if name == "root" else (a.astype(np.float64) if name == "t_birth" else a)
+        if self.x is not None:
+            out["x"] = np.stack([t[:n].double().cpu().numpy() for t in (self.x, self.y, self.z)], axis=1)
+        return out
+
+
+@dataclass
+class Fields:
+    """Per-particle (stride 1) or shared (stride 0) E and B of one species."""
+    ex: object
+    ey: object
+    ez: object
+    bx: object
+    by: object
+    bz: object
+    stride: int = 1
+
+    @classmethod
+    def from_array(cls, f, dtype=None, device="cuda"):
+        torch = _torch()
+        dtype = dtype or torch.float32
+        f = np.asarray(f, dtype=np.float64).reshape(-1, 6)
+        t = torch.as_tensor(f).to(device=device, dtype=dtype)
+        return cls(*[t[:, k].contiguous() for k in range(6)], stride=0 if f.shape[0] == 1 else 1)
+
+    def c(self) -> CFields:
+        return CFields(*[_ptr(t) for t in (self.ex, self.ey, self.ez, self.bx, self.by, self.bz)], self.stride)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t == torch.float32:
+        return F32
+    if t == torch.float64:
+        return F64
+    raise SfqedError(1, f"unsupported dtype {t}")
+
+
+def _ensemble(main: list, fields: list) -> CEnsemble:
+    e = CEnsemble()
+    e.dtype = _dtype_code(main[0].dtype)
+    for k in range(3):
+        e.s[k] = main[k].c()
+        e.f[k] = fields[k].c()
+    return e
+
+
+def step_cfg(emission=True, pair=True, push=True, gamma_min=1.0, max_events=1 << 20, profile=False) -> StepCfg:
+    cfg = StepCfg()
+    lib().qed_step_cfg_default(C.byref(cfg))
+    cfg.emission, cfg.pair, cfg.push = int(emission), int(pair), int(push)
+    cfg.gamma_min, cfg.max_events, cfg.profile = float(gamma_min), int(max_events), int(profile)
+    return cfg
+
+
+def init_tau(main: list, fields: list, seed: int, step_index: int, stream=None):
+    e = _ensemble(main, fields)
+    _check(lib().qed_init_tau(C.byref(e), C.c_uint64(seed), C.c_uint32(step_index), _stream(stream)))
+
+
+def step(tables: Tables, main: list, fields: list, app: list, dt: float, seed: int, step_index: int,
+         cfg: StepCfg | None = None, stream=None, check: bool = True) -> tuple[int, StepStats]:
+    """One global step (Algorithms 1 and 2).  Updates main/app in place and app counts."""
+    cfg = cfg if cfg is not None else step_cfg()
+    e = _ensemble(main, fields)
+    a = (CSpecies * 3)(*[s.c() for s in app])
+    for s in app:
+        s.count = 0
+    a = (CSpecies * 3)(*[s.c() for s in app])
+    st = StepStats()
+    rc = lib().qed_step(tables.handle, C.byref(cfg), C.byref(e), a, float(dt), C.c_uint64(seed),
+                        C.c_uint32(step_index), C.byref(st), _stream(stream))
+    for k in range(3):
+        app[k].count = int(a[k].count)
+    if check:
+        _check(rc)
+    return rc, st
+
+
+def merge(main: list, fields: list, app: list, stream=None):
+    e = _ensemble(main, fields)
+    a = (CSpecies * 3)(*[s.c() for s in app])
+    _check(lib().qed_merge(C.byref(e), a, _stream(stream)))
+    for k in range(3):
+        main[k].count = int(e.s[k].count)
+
+
+def eval_rate(tables: Tables, process: int, chi, energy, stream=None):
+    torch = _torch()
+    out = torch.empty_like(chi)
+    _check(lib().qed_eval_rate(tables.handle, process, _dtype_code(chi.dtype), _ptr(chi), _ptr(energy), _ptr(out),
+                               chi.numel(), _stream(stream)))
+    return out
+
+
+def eval_particles(tables: Tables, species: int, store: Store, fields: Fields, n: int | None = None, stream=None):
+    torch = _torch()
+    n = store.count if n is None else n
+    chi = torch.empty(n, dtype=store.dtype, device=store.px.device)
+    w = torch.empty_like(chi)
+    f = fields.c()
+    _check(lib().qed_eval_particles(tables.handle, species, _dtype_code(store.dtype), _ptr(store.px), _ptr(store.py),
+                                    _ptr(store.pz), C.byref(f), n, _ptr(chi), _ptr(w), _stream(stream)))
+    return chi, w
+
+
+def sample(tables: Tables, process: int, chi, k, stream=None):
+    """delta (emission) or xi (pairs) for raw 32-bit uniforms k (int32 tensor holding the bits)."""
+    torch = _torch()
+    out = torch.empty_like(chi)
+    _check(lib().qed_sample(tables.handle, process, _dtype_code(chi.dtype), _ptr(chi), _ptr(k), _ptr(out),
+                            chi.numel(), _stream(stream)))
+    return out

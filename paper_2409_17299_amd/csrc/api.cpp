@@ -1,0 +1,700 @@
+// api.cpp -- C ABI of libsfqed: argument checks, per-device scratch, the
+// generation-round driver of Algorithm 2 and the merge.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lib.h"
+#include "step.h"
+
+namespace sfqed {
+
+namespace {
+thread_local std::string g_error;
+}
+void set_error(const std::string& msg) { g_error = msg; }
+
+namespace {
+
+constexpr int kSlots = 3072;           // zeroed work counters per step
+constexpr int kCtrlWords = kSlots + 64;
+constexpr int kCurPhoton = kSlots + 0;  // append count of photons
+constexpr int kCurLepton = kSlots + 1;  // append count of electrons (= positrons)
+constexpr int kListLen = kSlots + 2;
+constexpr int kMergeCount = kSlots + 3;
+constexpr int kAliveCount = kSlots + 4;
+constexpr int kStats = kSlots + 8;      // 8 words
+
+// Library-owned scratch of one device: per-particle counts, offsets and event
+// list of the largest launch so far, look-back words, and a control block.
+struct Scratch {
+  int device = -1;
+  int64_t cap = 0;
+  int32_t* counts = nullptr;
+  int64_t* offsets = nullptr;
+  int32_t* list = nullptr;
+  int64_t tiles_cap = 0;
+  uint64_t* state_c = nullptr;
+  uint64_t* state_f = nullptr;
+  uint64_t* ctrl = nullptr;
+  uint32_t epoch = 0;
+  int num_cu = 0;
+  size_t max_lds = 0;
+  std::mutex mu;
+};
+
+std::mutex g_scratch_mu;
+std::vector<Scratch*> g_scratch;
+
+Scratch* scratch_for_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  for (Scratch* s : g_scratch)
+    if (s->device == dev) return s;
+  Scratch* s = new Scratch();
+  s->device = dev;
+  int v = 0;
+  hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+  s->num_cu = v > 0 ? v : 1;
+  hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  s->max_lds = v > 0 ? (size_t)v : 65536;
+  if (hipMalloc(&s->ctrl, sizeof(uint64_t) * kCtrlWords) != hipSuccess) {
+    delete s;
+    return nullptr;
+  }
+  hipMemset(s->ctrl, 0, sizeof(uint64_t) * kCtrlWords);
+  g_scratch.push_back(s);
+  return s;
+}
+
+qed_status ensure_scratch(Scratch* s, int64_t n) {
+  if (n > s->cap) {
+    const int64_t cap = std::max<int64_t>(n, s->cap * 3 / 2);
+    if (s->counts) {
+      SFQED_HIP(hipDeviceSynchronize());
+      hipFree(s->counts);
+      hipFree(s->offsets);
+      hipFree(s->list);
+      s->counts = nullptr;
+    }
+    SFQED_HIP(hipMalloc(&s->counts, sizeof(int32_t) * cap));
+    SFQED_HIP(hipMalloc(&s->offsets, sizeof(int64_t) * cap));
+    SFQED_HIP(hipMalloc(&s->list, sizeof(int32_t) * cap));
+    s->cap = cap;
+  }
+  const int64_t tiles = (std::max(n, s->cap) + kScanTile - 1) / kScanTile + 1;
+  if (tiles > s->tiles_cap) {
+    if (s->state_c) {
+      SFQED_HIP(hipDeviceSynchronize());
+      hipFree(s->state_c);
+      hipFree(s->state_f);
+    }
+    SFQED_HIP(hipMalloc(&s->state_c, sizeof(uint64_t) * tiles));
+    SFQED_HIP(hipMalloc(&s->state_f, sizeof(uint64_t) * tiles));
+    SFQED_HIP(hipMemset(s->state_c, 0, sizeof(uint64_t) * tiles));
+    SFQED_HIP(hipMemset(s->state_f, 0, sizeof(uint64_t) * tiles));
+    s->tiles_cap = tiles;
+    s->epoch = 0;
+  }
+  return QED_OK;
+}
+
+uint32_t next_epoch(Scratch* s) {
+  s->epoch = (s->epoch + 1) & 0xFFFFFFu;
+  if (s->epoch == 0) s->epoch = 1;
+  return s->epoch;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+template <typename T>
+SpeciesView<T> view_of(const qed_species& s) {
+  SpeciesView<T> v;
+  v.px = static_cast<T*>(s.px);
+  v.py = static_cast<T*>(s.py);
+  v.pz = static_cast<T*>(s.pz);
+  v.x = static_cast<T*>(s.x);
+  v.y = static_cast<T*>(s.y);
+  v.z = static_cast<T*>(s.z);
+  v.w = s.w;
+  v.tau = s.tau;
+  v.id = s.id;
+  v.alive = s.alive;
+  v.nev = s.nev;
+  v.root = s.root;
+  v.tb = static_cast<T*>(s.t_birth);
+  return v;
+}
+
+template <typename T>
+FieldView<T> fields_of(const qed_fields& f) {
+  FieldView<T> v;
+  v.ex = static_cast<const T*>(f.ex);
+  v.ey = static_cast<const T*>(f.ey);
+  v.ez = static_cast<const T*>(f.ez);
+  v.bx = static_cast<const T*>(f.bx);
+  v.by = static_cast<const T*>(f.by);
+  v.bz = static_cast<const T*>(f.bz);
+  v.stride = f.stride;
+  return v;
+}
+
+bool species_ok(const qed_species& s, bool photon, bool positions, bool is_append) {
+  if (s.count < 0 || s.capacity < s.count) return false;
+  if (s.capacity == 0) return true;
+  if (!s.px || !s.py || !s.pz || !s.w || !s.tau || !s.id) return false;
+  if (photon && !s.alive) return false;
+  const int nx = (s.x != nullptr) + (s.y != nullptr) + (s.z != nullptr);
+  if (nx != 0 && nx != 3) return false;
+  if ((nx == 3) != positions) return false;
+  if (is_append && (!s.root || !s.t_birth)) return false;
+  if (s.capacity >= (int64_t(1) << 30)) return false;  // root index field
+  return true;
+}
+
+bool fields_ok(const qed_fields& f, int64_t n) {
+  if (n == 0) return true;
+  if (!f.ex || !f.ey || !f.ez || !f.bx || !f.by || !f.bz) return false;
+  return f.stride == 0 || f.stride == 1;
+}
+
+struct Timer {
+  bool on;
+  hipStream_t st;
+  hipEvent_t a, b;
+  Timer(bool on_, hipStream_t s) : on(on_), st(s) {
+    if (on) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+    }
+  }
+  ~Timer() {
+    if (on) {
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+    }
+  }
+  void start() {
+    if (on) hipEventRecord(a, st);
+  }
+  double stop() {
+    if (!on) return 0.0;
+    hipEventRecord(b, st);
+    hipEventSynchronize(b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, a, b);
+    return ms;
+  }
+};
+
+// One launch (count, scan, write) over particles [begin, begin + n) of one
+// store.  Returns the kernel time when profiling.
+template <typename T>
+qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const qed_step_cfg* cfg,
+                      const qed_ensemble* ens, qed_species* app, int species, bool from_main, int64_t begin,
+                      int64_t n, double dt, uint64_t seed, uint32_t step, int* slot, bool positions,
+                      double* ms_total, double* ms_count, double* ms_write) {
+  if (n <= 0) return QED_OK;
+  qed_status rc = ensure_scratch(S, n);
+  if (rc != QED_OK) return rc;
+  if (*slot + 3 > kSlots) {
+    SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t) * kSlots, st));
+    *slot = 0;
+  }
+  const bool photon = species == 2;
+  StepArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.src = from_main ? view_of<T>(ens->s[species]) : view_of<T>(app[species]);
+  if (from_main) {
+    a.src.root = nullptr;
+    a.src.tb = nullptr;
+  }
+  a.species = species;
+  a.from_main = from_main ? 1 : 0;
+  a.begin = begin;
+  a.n = n;
+  for (int k = 0; k < 3; ++k) a.f[k] = fields_of<T>(ens->f[k]);
+  int64_t* cursor;
+  if (photon) {
+    a.out[0] = view_of<T>(app[0]);
+    a.out[1] = view_of<T>(app[1]);
+    a.out_cap = std::min(app[0].capacity, app[1].capacity);
+    cursor = reinterpret_cast<int64_t*>(S->ctrl + kCurLepton);
+  } else {
+    a.out[0] = view_of<T>(app[2]);
+    a.out_cap = app[2].capacity;
+    cursor = reinterpret_cast<int64_t*>(S->ctrl + kCurPhoton);
+  }
+  a.counts = S->counts;
+  a.offsets = S->offsets;
+  a.list = S->list;
+  a.list_len = reinterpret_cast<int64_t*>(S->ctrl + kListLen);
+  a.queue = reinterpret_cast<unsigned long long*>(S->ctrl + *slot);
+  a.stats = reinterpret_cast<unsigned long long*>(S->ctrl + kStats);
+  a.dt = dt;
+  a.seed = seed;
+  a.step = step;
+  a.emission = cfg->emission;
+  a.pair = cfg->pair;
+  a.push = cfg->push;
+  a.positions = positions ? 1 : 0;
+  a.gamma_min = cfg->gamma_min;
+  a.max_events = cfg->max_events;
+  a.tab = tab->view;
+
+  const int p = photon ? 1 : 0;
+  size_t lds = 0;
+  if (sizeof(T) == 4) lds = sizeof(float2) * tab->view.rate[p].n + sizeof(float) * tab->view.cdf[p].rows32 * tab->view.cdf[p].cols32;
+  const int per_cu = sizeof(T) == 4 ? std::max<int>(1, (int)(160 * 1024 / std::max<size_t>(lds, 1))) : 4;
+  const int max_grid = S->num_cu * std::min(per_cu, 2);
+  const int grid = (int)std::min<int64_t>((n + kStepThreads - 1) / kStepThreads, max_grid);
+
+  ScanArgs s;
+  s.counts = S->counts;
+  s.n = n;
+  s.offsets = S->offsets;
+  s.list = S->list;
+  s.cursor = cursor;
+  s.list_len = reinterpret_cast<int64_t*>(S->ctrl + kListLen);
+  s.state_c = S->state_c;
+  s.state_f = S->state_f;
+  s.epoch = next_epoch(S);
+  s.ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot + 2);
+  s.num_tiles = (n + kScanTile - 1) / kScanTile;
+  *slot += 3;
+
+  const bool prof = cfg->profile != 0;
+  Timer t0(prof, st);
+  t0.start();
+  hipError_t e = photon ? launch_count<T, true>(a, grid, lds, st) : launch_count<T, false>(a, grid, lds, st);
+  if (e != hipSuccess) {
+    set_error(std::string("count kernel: ") + hipGetErrorString(e));
+    return QED_ERR_HIP;
+  }
+  const double mc = t0.stop();
+  Timer t1(prof, st);
+  t1.start();
+  e = launch_scan(s, st);
+  if (e != hipSuccess) {
+    set_error(std::string("scan kernel: ") + hipGetErrorString(e));
+    return QED_ERR_HIP;
+  }
+  e = photon ? launch_write<T, true>(a, grid, lds, st) : launch_write<T, false>(a, grid, lds, st);
+  if (e != hipSuccess) {
+    set_error(std::string("write kernel: ") + hipGetErrorString(e));
+    return QED_ERR_HIP;
+  }
+  const double mw = t1.stop();
+  if (ms_total) *ms_total += mc + mw;
+  if (ms_count) *ms_count += mc;
+  if (ms_write) *ms_write += mw;
+  return QED_OK;
+}
+
+template <typename T>
+qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble* ens, qed_species* app,
+                     double dt, uint64_t seed, uint32_t step, qed_step_stats* stats, hipStream_t st) {
+  Scratch* S = scratch_for_current_device();
+  if (!S) {
+    set_error("no HIP device");
+    return QED_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t) * kCtrlWords, st));
+  int slot = 0;
+  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
+  qed_step_stats local;
+  std::memset(&local, 0, sizeof(local));
+  int64_t cur[2] = {0, 0};  // photons, leptons appended so far
+  auto read_cursors = [&]() -> qed_status {
+    int64_t h[2];
+    SFQED_HIP(hipMemcpyAsync(h, S->ctrl + kCurPhoton, sizeof(h), hipMemcpyDeviceToHost, st));
+    SFQED_HIP(hipStreamSynchronize(st));
+    cur[0] = h[0];
+    cur[1] = h[1];
+    return QED_OK;
+  };
+  const int64_t capg = app[2].capacity, capl = std::min(app[0].capacity, app[1].capacity);
+  double* ms_lep = &local.ms_lepton;
+  double* ms_pho = &local.ms_photon;
+  qed_status rc;
+  int64_t launches = 0;
+  auto launch = [&](int species, bool from_main, int64_t begin, int64_t n, double* msa, double* msb,
+                    double* msc) -> qed_status {
+    if (n <= 0) return QED_OK;
+    ++launches;
+    return run_launch<T>(S, st, tab, cfg, ens, app, species, from_main, begin, n, dt, seed, step, &slot, positions,
+                         msa, msb, msc);
+  };
+  // round 0: the input ensemble, then the photons its leptons emitted
+  double ms_main = 0.0, ms_count_main = 0.0, ms_write_main = 0.0;
+  if ((rc = launch(0, true, 0, ens->s[0].count, &ms_main, &ms_count_main, &ms_write_main)) != QED_OK) return rc;
+  if ((rc = launch(1, true, 0, ens->s[1].count, &ms_main, &ms_count_main, &ms_write_main)) != QED_OK) return rc;
+  *ms_lep += ms_main;
+  if ((rc = read_cursors()) != QED_OK) return rc;
+  local.n_children_main = cur[0];
+  int64_t g_done = 0;
+  bool overflow = cur[0] > capg;
+  if (!overflow) {
+    if ((rc = launch(2, true, 0, ens->s[2].count, ms_pho, nullptr, nullptr)) != QED_OK) return rc;
+    const int64_t g_hi = cur[0];
+    if ((rc = launch(2, false, 0, g_hi, ms_pho, nullptr, nullptr)) != QED_OK) return rc;
+    g_done = g_hi;
+    if ((rc = read_cursors()) != QED_OK) return rc;
+    overflow = cur[0] > capg || cur[1] > capl;
+  }
+  int64_t rounds = 1, l_done = 0;
+  while (!overflow && cur[1] > l_done) {
+    const int64_t l_hi = cur[1];
+    if ((rc = launch(0, false, l_done, l_hi - l_done, ms_lep, nullptr, nullptr)) != QED_OK) return rc;
+    if ((rc = launch(1, false, l_done, l_hi - l_done, ms_lep, nullptr, nullptr)) != QED_OK) return rc;
+    l_done = l_hi;
+    if ((rc = read_cursors()) != QED_OK) return rc;
+    if (cur[0] > capg) {
+      overflow = true;
+      break;
+    }
+    const int64_t g_hi = cur[0];
+    if ((rc = launch(2, false, g_done, g_hi - g_done, ms_pho, nullptr, nullptr)) != QED_OK) return rc;
+    g_done = g_hi;
+    if ((rc = read_cursors()) != QED_OK) return rc;
+    overflow = cur[0] > capg || cur[1] > capl;
+    ++rounds;
+  }
+  uint64_t dev_stats[8];
+  SFQED_HIP(hipMemcpyAsync(dev_stats, S->ctrl + kStats, sizeof(dev_stats), hipMemcpyDeviceToHost, st));
+  SFQED_HIP(hipStreamSynchronize(st));
+  local.n_emit = cur[0];
+  local.n_pair = cur[1];
+  local.n_new[0] = cur[1];
+  local.n_new[1] = cur[1];
+  local.n_new[2] = cur[0];
+  local.n_rounds = rounds;
+  local.max_events = (int64_t)dev_stats[kStatMaxEvents];
+  local.required_capacity[0] = cur[1];
+  local.required_capacity[1] = cur[1];
+  local.required_capacity[2] = cur[0];
+  local.n_launches = launches;
+  local.ms_lepton_main = ms_main;
+  local.ms_count_main = ms_count_main;
+  local.ms_write_main = ms_write_main;
+  local.n_lepton_main = ens->s[0].count + ens->s[1].count;
+  app[0].count = std::min(cur[1], app[0].capacity);
+  app[1].count = std::min(cur[1], app[1].capacity);
+  app[2].count = std::min(cur[0], app[2].capacity);
+  if (stats) *stats = local;
+  if (overflow) {
+    set_error("append capacity exceeded");
+    return QED_ERR_CAPACITY;
+  }
+  if (dev_stats[kStatCapped]) {
+    set_error("a particle reached max_events");
+    return QED_ERR_EVENT_CAP;
+  }
+  return QED_OK;
+}
+
+template <typename T>
+qed_status merge_impl(qed_ensemble* ens, const qed_species* app, hipStream_t st) {
+  Scratch* S = scratch_for_current_device();
+  if (!S) return QED_ERR_HIP;
+  std::lock_guard<std::mutex> lk(S->mu);
+  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
+  // leptons: append after the survivors (leptons do not die)
+  for (int s = 0; s < 2; ++s)
+    if (ens->s[s].count + app[s].count > ens->s[s].capacity) {
+      set_error("merge: lepton capacity");
+      return QED_ERR_CAPACITY;
+    }
+  // photons: count survivors first
+  SFQED_HIP(hipMemsetAsync(S->ctrl + kAliveCount, 0, sizeof(uint64_t), st));
+  SFQED_HIP(launch_count_alive(ens->s[2].alive, ens->s[2].count, reinterpret_cast<unsigned long long*>(S->ctrl + kAliveCount), st));
+  SFQED_HIP(launch_count_alive(app[2].alive, app[2].count, reinterpret_cast<unsigned long long*>(S->ctrl + kAliveCount), st));
+  uint64_t alive_total = 0;
+  SFQED_HIP(hipMemcpyAsync(&alive_total, S->ctrl + kAliveCount, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  SFQED_HIP(hipStreamSynchronize(st));
+  if ((int64_t)alive_total > ens->s[2].capacity) {
+    set_error("merge: photon capacity");
+    return QED_ERR_CAPACITY;
+  }
+  for (int s = 0; s < 2; ++s) {
+    const qed_species& m = ens->s[s];
+    const qed_species& a = app[s];
+    const int64_t n = a.count, o = m.count;
+    if (n == 0) continue;
+    const size_t sT = sizeof(T);
+    SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.px) + o, a.px, sT * n, hipMemcpyDeviceToDevice, st));
+    SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.py) + o, a.py, sT * n, hipMemcpyDeviceToDevice, st));
+    SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.pz) + o, a.pz, sT * n, hipMemcpyDeviceToDevice, st));
+    if (positions) {
+      SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.x) + o, a.x, sT * n, hipMemcpyDeviceToDevice, st));
+      SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.y) + o, a.y, sT * n, hipMemcpyDeviceToDevice, st));
+      SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.z) + o, a.z, sT * n, hipMemcpyDeviceToDevice, st));
+    }
+    SFQED_HIP(hipMemcpyAsync(m.w + o, a.w, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+    SFQED_HIP(hipMemcpyAsync(m.tau + o, a.tau, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    SFQED_HIP(hipMemcpyAsync(m.id + o, a.id, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, st));
+  }
+  const int64_t ntot = ens->s[2].count + app[2].count;
+  int64_t new_photons = 0;
+  if (ntot > 0) {
+    qed_status rc = ensure_scratch(S, 1);
+    if (rc != QED_OK) return rc;
+    const int64_t tiles = (ntot + kMergeThreads - 1) / kMergeThreads;
+    if (tiles > S->tiles_cap) {
+      if (S->state_c) {
+        SFQED_HIP(hipDeviceSynchronize());
+        hipFree(S->state_c);
+        hipFree(S->state_f);
+      }
+      SFQED_HIP(hipMalloc(&S->state_c, sizeof(uint64_t) * tiles));
+      SFQED_HIP(hipMalloc(&S->state_f, sizeof(uint64_t) * tiles));
+      SFQED_HIP(hipMemset(S->state_c, 0, sizeof(uint64_t) * tiles));
+      SFQED_HIP(hipMemset(S->state_f, 0, sizeof(uint64_t) * tiles));
+      S->tiles_cap = tiles;
+      S->epoch = 0;
+    }
+    SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t), st));
+    MergeArgs<T> m;
+    m.main = view_of<T>(ens->s[2]);
+    m.app = view_of<T>(app[2]);
+    m.n_main = ens->s[2].count;
+    m.n_app = app[2].count;
+    m.positions = positions ? 1 : 0;
+    m.state = S->state_c;
+    m.epoch = next_epoch(S);
+    m.ticket = reinterpret_cast<unsigned long long*>(S->ctrl);
+    m.num_tiles = tiles;
+    m.out_count = reinterpret_cast<int64_t*>(S->ctrl + kMergeCount);
+    SFQED_HIP(launch_merge_photons<T>(m, st));
+    SFQED_HIP(hipMemcpyAsync(&new_photons, S->ctrl + kMergeCount, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  }
+  SFQED_HIP(hipStreamSynchronize(st));
+  ens->s[0].count += app[0].count;
+  ens->s[1].count += app[1].count;
+  ens->s[2].count = new_photons;
+  return QED_OK;
+}
+
+}  // namespace
+}  // namespace sfqed
+
+using namespace sfqed;
+
+extern "C" {
+
+const char* qed_status_str(qed_status s) {
+  switch (s) {
+    case QED_OK: return "ok";
+    case QED_ERR_ARG: return "invalid argument";
+    case QED_ERR_CAPACITY: return "capacity exceeded";
+    case QED_ERR_HIP: return "HIP runtime error";
+    case QED_ERR_STATE: return "invalid state";
+    case QED_ERR_EVENT_CAP: return "max_events reached";
+  }
+  return "unknown status";
+}
+
+const char* qed_last_error(void) { return g_error.c_str(); }
+
+int32_t qed_abi_version(void) { return 1; }
+
+void qed_table_cfg_default(qed_table_cfg* c) {
+  if (!c) return;
+  c->rate_chi_min = 1e-7;
+  c->rate_chi_max = 1e5;
+  c->rate_nodes = 512;
+  c->rad_chi_min = 1e-4;
+  c->rad_chi_max = 1e4;
+  c->rad_rows = 70;
+  c->rad_cols = 265;
+  c->rad_x_min = -10.0;
+  c->rad_x_max = 23.0;
+  c->pair_chi_min = 1e-2;
+  c->pair_chi_max = 1e4;
+  c->pair_rows = 47;
+  c->pair_cols = 185;
+  c->pair_x_min = -23.0;
+  c->f64_refine = 4;
+}
+
+qed_status qed_build_rate_tables(const qed_table_cfg* cfg, void* stream, qed_tables** out) {
+  if (!cfg || !out) return QED_ERR_ARG;
+  const qed_table_cfg& c = *cfg;
+  auto range_ok = [](double lo, double hi) { return finite_pos(lo) && finite_pos(hi) && hi > lo; };
+  if (!range_ok(c.rate_chi_min, c.rate_chi_max) || !range_ok(c.rad_chi_min, c.rad_chi_max) ||
+      !range_ok(c.pair_chi_min, c.pair_chi_max) || c.rate_chi_max < 1e-3 || c.rate_nodes < 4 ||
+      c.rate_nodes > (1 << 16) || c.rad_rows < 4 || c.rad_cols < 4 || c.pair_rows < 4 || c.pair_cols < 4 ||
+      !(c.rad_x_max > c.rad_x_min) || !(c.pair_x_min < 0.0) || c.f64_refine < 1 || c.f64_refine > 16) {
+    set_error("invalid table configuration");
+    return QED_ERR_ARG;
+  }
+  const size_t lds_rad = sizeof(float2) * c.rate_nodes + sizeof(float) * (size_t)c.rad_rows * c.rad_cols;
+  const size_t lds_pair = sizeof(float2) * c.rate_nodes + sizeof(float) * (size_t)c.pair_rows * c.pair_cols;
+  if (lds_rad > 96 * 1024 || lds_pair > 96 * 1024) {
+    set_error("FP32 tables exceed 96 KiB of LDS");
+    return QED_ERR_ARG;
+  }
+  qed_tables* t = new qed_tables();
+  std::memset(t, 0, sizeof(*t));
+  hipGetDevice(&t->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  qed_status rc = build_tables(c, st, t);
+  if (rc == QED_OK && hipStreamSynchronize(st) != hipSuccess) {
+    set_error("table build failed");
+    rc = QED_ERR_HIP;
+  }
+  if (rc != QED_OK) {
+    if (t->mem) hipFree(t->mem);
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return QED_OK;
+}
+
+void qed_tables_free(qed_tables* t) {
+  if (!t) return;
+  if (t->mem) hipFree(t->mem);
+  delete t;
+}
+
+qed_status qed_tables_export(const qed_tables* t, int which, void* dst, size_t* bytes) {
+  if (!t || which < 0 || which > 7 || !bytes) return QED_ERR_ARG;
+  const size_t len = t->len[which];
+  if (!dst) {
+    *bytes = len;
+    return QED_OK;
+  }
+  if (*bytes != len) return QED_ERR_ARG;
+  SFQED_HIP(hipMemcpy(dst, static_cast<const char*>(t->mem) + t->off[which], len, hipMemcpyDeviceToHost));
+  return QED_OK;
+}
+
+qed_status qed_tables_geometry(const qed_tables* t, double* out, int n) {
+  // [nseg0, s_lo0, nseg1, s_lo1, herm_n, rows32_0, cols32_0, rows64_0, cols64_0, s0_0, s1_0, x0_0, x1_0,
+  //  rows32_1, cols32_1, rows64_1, cols64_1, s0_1, s1_1, x0_1, x1_1]
+  if (!t || !out || n < 21) return QED_ERR_ARG;
+  const TableGeom& g = t->geom;
+  double v[21] = {(double)g.nseg[0], g.cheb_s_lo[0], (double)g.nseg[1], g.cheb_s_lo[1], (double)g.herm_n,
+                  (double)g.rows32[0], (double)g.cols32[0], (double)g.rows64[0], (double)g.cols64[0], g.s0[0],
+                  g.s1[0], g.x0[0], g.x1[0], (double)g.rows32[1], (double)g.cols32[1], (double)g.rows64[1],
+                  (double)g.cols64[1], g.s0[1], g.s1[1], g.x0[1], g.x1[1]};
+  std::memcpy(out, v, sizeof(v));
+  return QED_OK;
+}
+
+void qed_step_cfg_default(qed_step_cfg* c) {
+  if (!c) return;
+  c->emission = 1;
+  c->pair = 1;
+  c->push = 1;
+  c->sampler = QED_SAMPLER_TABLE;
+  c->mlp = nullptr;
+  c->gamma_min = 1.0;
+  c->max_events = 1 << 20;
+  c->profile = 0;
+}
+
+qed_status qed_init_tau(qed_ensemble* ens, uint64_t seed, uint32_t step, void* stream) {
+  if (!ens) return QED_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int s = 0; s < 3; ++s) {
+    const qed_species& sp = ens->s[s];
+    if (sp.count == 0) continue;
+    if (!sp.tau || !sp.id || sp.count < 0) return QED_ERR_ARG;
+    SFQED_HIP(launch_init_tau<float>(sp.tau, sp.id, sp.count, seed, step, st));
+  }
+  return QED_OK;
+}
+
+qed_status qed_step(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble* ens, qed_species app[3], double dt,
+                    uint64_t seed, uint32_t step, qed_step_stats* stats, void* stream) {
+  if (!tab || !cfg || !ens || !app) {
+    set_error("null argument");
+    return QED_ERR_ARG;
+  }
+  if (!finite_pos(dt) || (ens->dtype != QED_F32 && ens->dtype != QED_F64) || !(cfg->gamma_min >= 1.0) ||
+      cfg->max_events < 1 || cfg->sampler != QED_SAMPLER_TABLE) {
+    set_error("invalid step configuration");
+    return QED_ERR_ARG;
+  }
+  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
+  for (int s = 0; s < 3; ++s) {
+    if (!species_ok(ens->s[s], s == 2, positions, false) || !species_ok(app[s], s == 2, positions, true) ||
+        !fields_ok(ens->f[s], ens->s[s].count)) {
+      set_error("invalid species " + std::to_string(s));
+      return QED_ERR_ARG;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ens->dtype == QED_F32) return step_impl<float>(tab, cfg, ens, app, dt, seed, step, stats, st);
+  return step_impl<double>(tab, cfg, ens, app, dt, seed, step, stats, st);
+}
+
+qed_status qed_merge(qed_ensemble* ens, const qed_species app[3], void* stream) {
+  if (!ens || !app) return QED_ERR_ARG;
+  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
+  for (int s = 0; s < 3; ++s) {
+    if (!species_ok(ens->s[s], s == 2, positions, false) || !species_ok(app[s], s == 2, positions, false))
+      return QED_ERR_ARG;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ens->dtype == QED_F32) return merge_impl<float>(ens, app, st);
+  if (ens->dtype == QED_F64) return merge_impl<double>(ens, app, st);
+  return QED_ERR_ARG;
+}
+
+qed_status qed_eval_rate(const qed_tables* t, int process, qed_dtype dtype, const void* chi, const void* energy,
+                         void* w_out, int64_t n, void* stream) {
+  if (!t || (process != 0 && process != 1) || n < 0 || (n > 0 && (!chi || !energy || !w_out))) return QED_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QED_F32)
+    SFQED_HIP(launch_eval_rate<float>(t->view, process, (const float*)chi, (const float*)energy, (float*)w_out, n, st));
+  else if (dtype == QED_F64)
+    SFQED_HIP(launch_eval_rate<double>(t->view, process, (const double*)chi, (const double*)energy, (double*)w_out, n,
+                                       st));
+  else
+    return QED_ERR_ARG;
+  return QED_OK;
+}
+
+qed_status qed_eval_particles(const qed_tables* t, int species, qed_dtype dtype, const void* px, const void* py,
+                              const void* pz, const qed_fields* f, int64_t n, void* chi_out, void* w_out,
+                              void* stream) {
+  if (!t || species < 0 || species > 2 || !f || n < 0 || (n > 0 && (!px || !py || !pz || !fields_ok(*f, n))))
+    return QED_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QED_F32)
+    SFQED_HIP(launch_eval_particles<float>(t->view, species, (const float*)px, (const float*)py, (const float*)pz,
+                                           fields_of<float>(*f), n, (float*)chi_out, (float*)w_out, st));
+  else if (dtype == QED_F64)
+    SFQED_HIP(launch_eval_particles<double>(t->view, species, (const double*)px, (const double*)py,
+                                            (const double*)pz, fields_of<double>(*f), n, (double*)chi_out,
+                                            (double*)w_out, st));
+  else
+    return QED_ERR_ARG;
+  return QED_OK;
+}
+
+qed_status qed_sample(const qed_tables* t, int process, qed_dtype dtype, const void* chi, const uint32_t* k,
+                      void* out, int64_t n, void* stream) {
+  if (!t || (process != 0 && process != 1) || n < 0 || (n > 0 && (!chi || !k || !out))) return QED_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QED_F32)
+    SFQED_HIP(launch_sample<float>(t->view, process, (const float*)chi, k, (float*)out, n, st));
+  else if (dtype == QED_F64)
+    SFQED_HIP(launch_sample<double>(t->view, process, (const double*)chi, k, (double*)out, n, st));
+  else
+    return QED_ERR_ARG;
+  return QED_OK;
+}
+
+}  // extern "C"

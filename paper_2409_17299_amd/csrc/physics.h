@@ -1,0 +1,306 @@
+// physics.h -- per-particle device functions of the event generator:
+// chi, rates from the tables, inverse-CDF samplers, Boris push.
+#pragma once
+
+#include "common.h"
+
+namespace sfqed {
+
+// ---------------------------------------------------------------------------
+// chi = sqrt((e E + p x B)^2 - (p.E)^2) with e = gamma for leptons and
+// e = |k| for photons (the quantum parameter of a particle in E, B).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T chi_of(const T p[3], T e, const T E[3], const T B[3]) {
+  const T ax = e * E[0] + (p[1] * B[2] - p[2] * B[1]);
+  const T ay = e * E[1] + (p[2] * B[0] - p[0] * B[2]);
+  const T az = e * E[2] + (p[0] * B[1] - p[1] * B[0]);
+  const T b = p[0] * E[0] + p[1] * E[1] + p[2] * E[2];
+  const T c2 = ax * ax + ay * ay + az * az - b * b;
+  return c2 > T(0) ? sqrt(c2) : T(0);
+}
+
+// Boris scheme over h for charge q: half electric kick, rotation in B about
+// the mid-step Lorentz factor, half electric kick.
+template <typename T>
+__device__ __forceinline__ void boris(T p[3], T q, const T E[3], const T B[3], T h) {
+  const T qh2 = T(0.5) * q * h;
+  T u[3] = {p[0] + qh2 * E[0], p[1] + qh2 * E[1], p[2] + qh2 * E[2]};
+  const T g = sqrt(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const T f = qh2 / g;
+  const T t[3] = {f * B[0], f * B[1], f * B[2]};
+  const T sc = T(2) / (T(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  const T v[3] = {u[0] + (u[1] * t[2] - u[2] * t[1]), u[1] + (u[2] * t[0] - u[0] * t[2]),
+                  u[2] + (u[0] * t[1] - u[1] * t[0])};
+  const T s[3] = {sc * t[0], sc * t[1], sc * t[2]};
+  u[0] += v[1] * s[2] - v[2] * s[1];
+  u[1] += v[2] * s[0] - v[0] * s[2];
+  u[2] += v[0] * s[1] - v[1] * s[0];
+  p[0] = u[0] + qh2 * E[0];
+  p[1] = u[1] + qh2 * E[1];
+  p[2] = u[2] + qh2 * E[2];
+}
+
+// ---------------------------------------------------------------------------
+// Rates.  g(s), s = ln chi, is tabulated:
+//   emission: g = ln(W_rad gamma / (alpha chi))
+//   pairs:    g = ln(W_pair eps / (alpha chi)) + 8 / (3 chi)
+// Below the table emission uses the two leading terms of the classical series
+// W gamma/alpha = 5 chi/(2 sqrt3) (1 - 8 sqrt3 chi/15) and pairs are zero;
+// above it ln(W/chi) continues with the chi^(-1/3) slope of both limits.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double cheb_clenshaw(const double* c, double x) {
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int j = kChebDeg; j >= 1; --j) {
+    const double b0 = fma(2.0 * x, b1, c[j] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fma(x, b1, 0.5 * c[0] - b2);
+}
+
+__device__ __forceinline__ double cheb_g(const RateView& r, double s) {
+  const double u = (s - r.s_lo) * (1.0 / kChebSegWidth);
+  int k = (int)floor(u);
+  k = k < 0 ? 0 : (k >= r.nseg ? r.nseg - 1 : k);
+  const double x = 2.0 * (u - k) - 1.0;
+  return cheb_clenshaw(r.cheb + k * kChebN, x);
+}
+
+__device__ __forceinline__ double rate_rad64(const RateView& r, double chi, double gamma) {
+  if (!(chi > 0.0)) return 0.0;
+  const double s = log(chi);
+  const double s_hi = r.s_lo + r.nseg * kChebSegWidth;
+  double g;
+  if (s < r.s_lo)
+    g = log(5.0 / (2.0 * kSqrt3)) + log1p(-(8.0 * kSqrt3 / 15.0) * chi);
+  else if (s > s_hi)
+    g = cheb_g(r, s_hi) - (s - s_hi) * (1.0 / 3.0);
+  else
+    g = cheb_g(r, s);
+  return kAlpha / gamma * chi * exp(g);
+}
+
+__device__ __forceinline__ double rate_pair64(const RateView& r, double chi, double eps) {
+  if (!(chi > 0.0)) return 0.0;
+  const double s = log(chi);
+  if (s < r.s_lo) return 0.0;
+  const double s_hi = r.s_lo + r.nseg * kChebSegWidth;
+  double lnf;  // ln(W eps / (alpha chi))
+  if (s > s_hi) {
+    const double chi_hi = exp(s_hi);
+    lnf = cheb_g(r, s_hi) - 8.0 / (3.0 * chi_hi) - (s - s_hi) * (1.0 / 3.0);
+  } else {
+    lnf = cheb_g(r, s) - 8.0 / (3.0 * chi);
+  }
+  return kAlpha / eps * chi * exp(lnf);
+}
+
+// cubic Hermite on a uniform grid (values and h-scaled slopes)
+__device__ __forceinline__ float herm_g(const float2* h, int n, float t) {
+  int i = (int)t;
+  i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
+  const float u = t - (float)i;
+  const float2 a = h[i], b = h[i + 1];
+  const float u2 = u * u, u3 = u2 * u;
+  const float h00 = 2.f * u3 - 3.f * u2 + 1.f, h10 = u3 - 2.f * u2 + u;
+  const float h01 = -2.f * u3 + 3.f * u2, h11 = u3 - u2;
+  return h00 * a.x + h10 * a.y + h01 * b.x + h11 * b.y;
+}
+
+// FP32 emission rate; `herm` may point to LDS.
+__device__ __forceinline__ float rate_rad32(const float2* herm, int n, float s0, float inv_h, float chi,
+                                            float gamma) {
+  if (!(chi > 0.f)) return 0.f;
+  const float s = logf(chi);
+  const float t = (s - s0) * inv_h;
+  float g;
+  if (t < 0.f) {
+    g = 0.3669845875401003f + log1pf(-0.9237604307034012f * chi);  // ln(5/(2 sqrt3)), 8 sqrt3/15
+  } else if (t > (float)(n - 1)) {
+    const float th = (float)(n - 1);
+    g = herm_g(herm, n, th) - (t - th) / (3.f * inv_h);
+  } else {
+    g = herm_g(herm, n, t);
+  }
+  return (float)kAlpha / gamma * chi * expf(g);
+}
+
+// FP32 pair rate.  exp(g - 8/(3 chi)) with the large exponent split so that
+// its rounding does not become a relative error of the rate.
+__device__ __forceinline__ float rate_pair32(const float2* herm, int n, float s0, float inv_h, float chi,
+                                             float eps) {
+  if (!(chi > 0.f)) return 0.f;
+  const float s = logf(chi);
+  const float t = (s - s0) * inv_h;
+  if (t < 0.f) return 0.f;
+  float g;
+  if (t > (float)(n - 1)) {
+    const float th = (float)(n - 1);
+    g = herm_g(herm, n, th) - (t - th) / (3.f * inv_h);
+  } else {
+    g = herm_g(herm, n, t);
+  }
+  const float c_hi = 2.6666667461395264f;        // 8/3 rounded to FP32
+  const float c_lo = -7.947286206899662e-08f;    // 8/3 - c_hi
+  const float qh = c_hi / chi;
+  const float ql = (fmaf(-qh, chi, c_hi) + c_lo) / chi;  // 8/(3 chi) = qh + ql
+  const float e = g - qh;
+  const float bv = e - g;
+  const float err = (g - (e - bv)) + (-qh - bv);          // two-sum error of g - qh
+  return (float)kAlpha / eps * chi * expf(e) * (1.f + (err - ql));
+}
+
+// ---------------------------------------------------------------------------
+// Inverse-CDF samplers.  Tables hold q on a uniform (s = ln chi, x = logit r)
+// grid; 4 x 4 cubic Lagrange interpolation (stencil shifted inwards at the
+// edges).  Emission: q = logit(delta) - s; below the x grid q continues as
+// q(x0) + 3 (ln r - ln r0) (delta ~ r^3 for r -> 0); below the chi grid q is
+// linear in chi between the first two rows (the classical limit is chi
+// independent); above the chi grid chi is clamped.  Pairs: q = logit(xi) for
+// r <= 1/2, mirrored for r > 1/2.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void lag4(T t, T w[4]) {
+  const T tm1 = t - T(1), tm2 = t - T(2), tp1 = t + T(1);
+  w[0] = -t * tm1 * tm2 * T(1.0 / 6.0);
+  w[1] = tp1 * tm1 * tm2 * T(0.5);
+  w[2] = -tp1 * t * tm2 * T(0.5);
+  w[3] = tp1 * t * tm1 * T(1.0 / 6.0);
+}
+
+// cubic in x along one row
+template <typename T, typename P>
+__device__ __forceinline__ T row_interp(const P* row, int cols, T ux) {
+  int j = (int)floor(ux);
+  j = j < 1 ? 1 : (j > cols - 3 ? cols - 3 : j);
+  T w[4];
+  lag4<T>(ux - T(j), w);
+  return w[0] * (T)row[j - 1] + w[1] * (T)row[j] + w[2] * (T)row[j + 1] + w[3] * (T)row[j + 2];
+}
+
+template <typename T, typename P>
+__device__ __forceinline__ T grid_interp(const P* tab, int rows, int cols, T us, T ux) {
+  int i = (int)floor(us);
+  i = i < 1 ? 1 : (i > rows - 3 ? rows - 3 : i);
+  int j = (int)floor(ux);
+  j = j < 1 ? 1 : (j > cols - 3 ? cols - 3 : j);
+  T ws[4], wx[4];
+  lag4<T>(us - T(i), ws);
+  lag4<T>(ux - T(j), wx);
+  T acc = T(0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const P* r = tab + (i - 1 + a) * cols + (j - 1);
+    const T v = wx[0] * (T)r[0] + wx[1] * (T)r[1] + wx[2] * (T)r[2] + wx[3] * (T)r[3];
+    acc += ws[a] * v;
+  }
+  return acc;
+}
+
+// ln r and ln(1 - r) of r = (k + 1/2) 2^-32
+__device__ __forceinline__ void log_r32(uint32_t k, float& lr, float& lrc) {
+  lr = logf((float)k + 0.5f) - 22.18070977791825f;      // 32 ln 2
+  lrc = logf((float)(~k) + 0.5f) - 22.18070977791825f;
+}
+__device__ __forceinline__ void log_r64(uint32_t k, double& lr, double& lrc) {
+  lr = log((double)k + 0.5) - 32.0 * kLn2;
+  lrc = log((double)(~k) + 0.5) - 32.0 * kLn2;
+}
+
+// Emission: delta and 1 - delta.  `tab` is the FP32 grid (LDS or global).
+__device__ __forceinline__ void sample_rad32(const float* tab, const CdfView& c, float chi, uint32_t k, float& d,
+                                             float& omd) {
+  float lr, lrc;
+  log_r32(k, lr, lrc);
+  const float x = lr - lrc;
+  float ux = (x - c.x0_32) * c.inv_hx32;
+  float extra = 0.f;
+  if (ux < 0.f) {
+    const float lr0 = -log1pf(expf(-c.x0_32));
+    extra = 3.f * (lr - lr0);
+    ux = 0.f;
+  }
+  ux = fminf(ux, (float)(c.cols32 - 1));
+  const float s_max = c.s0_32 + (float)(c.rows32 - 1) / c.inv_hs32;
+  const float s = fminf(logf(chi), s_max);  // above the grid chi is clamped
+  const float us = (s - c.s0_32) * c.inv_hs32;
+  float q;
+  if (us < 0.f) {
+    const float q0 = row_interp<float, float>(tab, c.cols32, ux);
+    const float q1 = row_interp<float, float>(tab + c.cols32, c.cols32, ux);
+    const float chi1 = (float)c.chi_lo * expf(1.f / c.inv_hs32);
+    q = q0 + (chi - (float)c.chi_lo) / (chi1 - (float)c.chi_lo) * (q1 - q0);
+  } else {
+    q = grid_interp<float, float>(tab, c.rows32, c.cols32, us, ux);
+  }
+  const float z = q + extra + s;
+  d = 1.f / (1.f + expf(-z));
+  omd = 1.f / (1.f + expf(z));
+}
+
+__device__ __forceinline__ void sample_rad64(const CdfView& c, double chi, uint32_t k, double& d, double& omd) {
+  double lr, lrc;
+  log_r64(k, lr, lrc);
+  const double x = lr - lrc;
+  double ux = (x - c.x0_64) * c.inv_hx64;
+  double extra = 0.0;
+  if (ux < 0.0) {
+    const double lr0 = -log1p(exp(-c.x0_64));
+    extra = 3.0 * (lr - lr0);
+    ux = 0.0;
+  }
+  ux = fmin(ux, (double)(c.cols64 - 1));
+  const double s_max = c.s0_64 + (double)(c.rows64 - 1) / c.inv_hs64;
+  const double s = fmin(log(chi), s_max);
+  const double us = (s - c.s0_64) * c.inv_hs64;
+  double q;
+  if (us < 0.0) {
+    const double q0 = row_interp<double, double>(c.f64, c.cols64, ux);
+    const double q1 = row_interp<double, double>(c.f64 + c.cols64, c.cols64, ux);
+    const double chi1 = c.chi_lo * exp(1.0 / c.inv_hs64);
+    q = q0 + (chi - c.chi_lo) / (chi1 - c.chi_lo) * (q1 - q0);
+  } else {
+    q = grid_interp<double, double>(c.f64, c.rows64, c.cols64, us, ux);
+  }
+  const double z = q + extra + s;
+  d = 1.0 / (1.0 + exp(-z));
+  omd = 1.0 / (1.0 + exp(z));
+}
+
+// Pairs: xi (electron) and 1 - xi (positron).
+__device__ __forceinline__ void sample_pair32(const float* tab, const CdfView& c, float chi, uint32_t k, float& xi,
+                                              float& omx) {
+  float lr, lrc;
+  log_r32(k, lr, lrc);
+  const float x = lr - lrc;
+  const float xa = -fabsf(x);
+  float ux = fmaxf((xa - c.x0_32) * c.inv_hx32, 0.f);
+  ux = fminf(ux, (float)(c.cols32 - 1));
+  float us = (logf(chi) - c.s0_32) * c.inv_hs32;
+  us = fminf(fmaxf(us, 0.f), (float)(c.rows32 - 1));
+  float q = grid_interp<float, float>(tab, c.rows32, c.cols32, us, ux);
+  q = fminf(q, 0.f);
+  const float qq = x > 0.f ? -q : q;
+  xi = 1.f / (1.f + expf(-qq));
+  omx = 1.f / (1.f + expf(qq));
+}
+
+__device__ __forceinline__ void sample_pair64(const CdfView& c, double chi, uint32_t k, double& xi, double& omx) {
+  double lr, lrc;
+  log_r64(k, lr, lrc);
+  const double x = lr - lrc;
+  const double xa = -fabs(x);
+  double ux = fmax((xa - c.x0_64) * c.inv_hx64, 0.0);
+  ux = fmin(ux, (double)(c.cols64 - 1));
+  double us = (log(chi) - c.s0_64) * c.inv_hs64;
+  us = fmin(fmax(us, 0.0), (double)(c.rows64 - 1));
+  double q = grid_interp<double, double>(c.f64, c.rows64, c.cols64, us, ux);
+  q = fmin(q, 0.0);
+  const double qq = x > 0.0 ? -q : q;
+  xi = 1.0 / (1.0 + exp(-qq));
+  omx = 1.0 / (1.0 + exp(qq));
+}
+
+}  // namespace sfqed

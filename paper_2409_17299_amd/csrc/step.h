@@ -1,0 +1,92 @@
+// step.h -- kernel argument blocks and launchers of the step (host + device).
+#pragma once
+
+#include "common.h"
+
+namespace sfqed {
+
+constexpr int kStepThreads = 512;   // step kernels: 8 waves per block
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kMergeThreads = 256;
+
+// device statistics words
+constexpr int kStatMaxEvents = 0;
+constexpr int kStatCapped = 1;
+
+template <typename T>
+struct StepArgs {
+  SpeciesView<T> src;
+  int32_t species;    // species of src (0 e-, 1 e+, 2 photon)
+  int32_t from_main;  // 1: src is the input ensemble (root = species << 30 | index)
+  int64_t begin, n;   // particles [begin, begin + n) of src
+  FieldView<T> f[3];
+  SpeciesView<T> out[2];  // leptons: out[0] photons; photons: out[0] e-, out[1] e+
+  int64_t out_cap;
+  int32_t* counts;    // [n]
+  int64_t* offsets;   // [n]
+  int32_t* list;      // [n]
+  const int64_t* list_len;
+  unsigned long long* queue;  // [2] work counters of the count and write kernels (zero at launch)
+  unsigned long long* stats;
+  double dt;
+  uint64_t seed;
+  uint32_t step;
+  int32_t emission, pair, push, positions;
+  double gamma_min;
+  int64_t max_events;
+  TableView tab;
+};
+
+struct ScanArgs {
+  const int32_t* counts;
+  int64_t n;
+  int64_t* offsets;
+  int32_t* list;
+  int64_t* cursor;    // in: append count before the launch; out: after
+  int64_t* list_len;
+  uint64_t* state_c;  // look-back words, one per tile
+  uint64_t* state_f;
+  uint32_t epoch;
+  unsigned long long* ticket;  // zero at launch
+  int64_t num_tiles;
+};
+
+template <typename T>
+struct MergeArgs {
+  SpeciesView<T> main, app;
+  int64_t n_main, n_app;
+  int32_t positions;
+  uint64_t* state;
+  uint32_t epoch;
+  unsigned long long* ticket;
+  int64_t num_tiles;
+  int64_t* out_count;
+};
+
+template <typename T, bool kPhoton>
+hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st);
+template <typename T, bool kPhoton>
+hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st);
+hipError_t launch_scan(const ScanArgs& s, hipStream_t st);
+template <typename T>
+hipError_t launch_merge_photons(const MergeArgs<T>& a, hipStream_t st);
+hipError_t launch_count_alive(const uint8_t* alive, int64_t n, unsigned long long* out, hipStream_t st);
+template <typename T>
+hipError_t launch_init_tau(double* tau, const uint64_t* id, int64_t n, uint64_t seed, uint32_t step, hipStream_t st);
+template <typename T>
+hipError_t launch_eval_rate(const TableView& tab, int process, const T* chi, const T* e, T* out, int64_t n,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_eval_particles(const TableView& tab, int species, const T* px, const T* py, const T* pz,
+                                 const FieldView<T>& f, int64_t n, T* chi, T* w, hipStream_t st);
+template <typename T>
+hipError_t launch_sample(const TableView& tab, int process, const T* chi, const uint32_t* k, T* out, int64_t n,
+                         hipStream_t st);
+
+// occupancy helpers (api.cpp)
+template <typename T, bool kPhoton>
+const void* count_kernel_ptr();
+
+}  // namespace sfqed

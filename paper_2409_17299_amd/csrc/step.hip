@@ -1,0 +1,729 @@
+// step.hip -- the event-generator step on the GPU.
+//
+// One launch processes a contiguous range of one species (Algorithm 1 for
+// every particle of the range; Algorithm 2 is the host loop over rounds in
+// api.cpp).  A launch is three kernels:
+//   count: every lane runs the sub-cycle loop of one particle, one sub-cycle
+//          per loop trip; a lane whose particle reached the end of the step
+//          takes the next one from a global queue (one atomic per wave), so
+//          lanes stay busy while the event counts of particles differ -- the
+//          role the paper's SortHandledParticles plays for a SIMD chunk
+//          (Sec. 4.3).  It records each particle's event count and writes the
+//          final state of particles without events.
+//   scan:  exclusive prefix sum of the counts (single pass, decoupled
+//          look-back between tiles) -> the append offset of every particle's
+//          first child, and the list of particles with events.
+//   write: re-runs the particles with events (same draws, same arithmetic)
+//          and writes their children at the final offsets and their final
+//          state.
+// The append order therefore is: particles in index order, children of one
+// particle in event order -- the same for every run and every grid size.
+
+#include "lib.h"
+#include "physics.h"
+#include "step.h"
+
+namespace sfqed {
+
+// ------------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// ------------------------------------------------------------------ look-back
+// State word: [epoch:24][flag:2][value:38]; flag 1 = aggregate, 2 = inclusive prefix.
+constexpr uint64_t kValMask = (1ull << 38) - 1;
+
+__device__ __forceinline__ void lb_publish(uint64_t* st, uint32_t epoch, uint64_t flag, uint64_t val) {
+  const uint64_t v = ((uint64_t)epoch << 40) | (flag << 38) | (val > kValMask ? kValMask : val);
+  __hip_atomic_store(st, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Run by one thread per tile.  Returns the exclusive prefix of the tile
+// (tile 0's prefix is `base`).
+__device__ int64_t lookback(uint64_t* st, int64_t tile, int64_t agg, int64_t base, uint32_t epoch) {
+  if (tile == 0) {
+    lb_publish(st, epoch, 2, (uint64_t)(base + agg));
+    return base;
+  }
+  lb_publish(st + tile, epoch, 1, (uint64_t)agg);
+  int64_t excl = 0;
+  int64_t k = tile - 1;
+  while (true) {
+    const uint64_t v = __hip_atomic_load(st + k, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t ep = (uint32_t)(v >> 40);
+    const uint32_t fl = (uint32_t)((v >> 38) & 3);
+    if (ep != epoch || fl == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += (int64_t)(v & kValMask);
+    if (fl == 2) break;
+    --k;
+  }
+  lb_publish(st + tile, epoch, 2, (uint64_t)(excl + agg));
+  return excl;
+}
+
+// ------------------------------------------------------------------ particle state
+template <typename T>
+struct Lane {
+  int64_t k;
+  T p[3], x[3], E[3], B[3];
+  double tau;
+  T t;
+  uint64_t id;
+  uint32_t root;
+  float w;
+  int32_t j;
+  bool capped;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<T>& L) {
+  const int64_t i = a.begin + k;
+  const SpeciesView<T>& s = a.src;
+  L.k = k;
+  L.p[0] = s.px[i];
+  L.p[1] = s.py[i];
+  L.p[2] = s.pz[i];
+  if (a.positions) {
+    L.x[0] = s.x[i];
+    L.x[1] = s.y[i];
+    L.x[2] = s.z[i];
+  } else {
+    L.x[0] = L.x[1] = L.x[2] = T(0);
+  }
+  L.tau = s.tau[i];
+  L.id = s.id[i];
+  L.w = s.w[i];
+  L.root = a.from_main ? (((uint32_t)a.species << 30) | (uint32_t)i) : s.root[i];
+  L.t = s.tb ? s.tb[i] : T(0);
+  const uint32_t sp = L.root >> 30;
+  const int64_t idx = (int64_t)(L.root & 0x3FFFFFFFu);
+  const FieldView<T>& f0 = a.f[0];
+  const FieldView<T>& f1 = a.f[1];
+  const FieldView<T>& f2 = a.f[2];
+  const T* ex = sp == 0 ? f0.ex : (sp == 1 ? f1.ex : f2.ex);
+  const T* ey = sp == 0 ? f0.ey : (sp == 1 ? f1.ey : f2.ey);
+  const T* ez = sp == 0 ? f0.ez : (sp == 1 ? f1.ez : f2.ez);
+  const T* bx = sp == 0 ? f0.bx : (sp == 1 ? f1.bx : f2.bx);
+  const T* by = sp == 0 ? f0.by : (sp == 1 ? f1.by : f2.by);
+  const T* bz = sp == 0 ? f0.bz : (sp == 1 ? f1.bz : f2.bz);
+  const int64_t st = sp == 0 ? f0.stride : (sp == 1 ? f1.stride : f2.stride);
+  const int64_t o = st ? idx : 0;
+  L.E[0] = ex[o];
+  L.E[1] = ey[o];
+  L.E[2] = ez[o];
+  L.B[0] = bx[o];
+  L.B[1] = by[o];
+  L.B[2] = bz[o];
+  L.j = 0;
+  L.capped = false;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_final(const StepArgs<T>& a, const Lane<T>& L, bool momentum) {
+  const int64_t i = a.begin + L.k;
+  const SpeciesView<T>& s = a.src;
+  if (momentum) {
+    s.px[i] = L.p[0];
+    s.py[i] = L.p[1];
+    s.pz[i] = L.p[2];
+  }
+  if (a.positions) {
+    s.x[i] = L.x[0];
+    s.y[i] = L.x[1];
+    s.z[i] = L.x[2];
+  }
+  s.tau[i] = L.tau;
+}
+
+// Tables as the kernels see them: FP32 tables staged in LDS, FP64 in HBM.
+struct LdsTables {
+  const float2* herm;
+  const float* cdf;
+};
+
+template <typename T>
+__device__ __forceinline__ T rate_of(const StepArgs<T>& a, const LdsTables& lt, int process, T chi, T energy) {
+  if constexpr (sizeof(T) == 4) {
+    const RateView& r = a.tab.rate[process];
+    return process == 0 ? rate_rad32(lt.herm, r.n, r.hs_lo, r.inv_h, chi, energy)
+                        : rate_pair32(lt.herm, r.n, r.hs_lo, r.inv_h, chi, energy);
+  } else {
+    return process == 0 ? rate_rad64(a.tab.rate[0], chi, energy) : rate_pair64(a.tab.rate[1], chi, energy);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void sample_of(const StepArgs<T>& a, const LdsTables& lt, int process, T chi, uint32_t k,
+                                          T& v, T& omv) {
+  if constexpr (sizeof(T) == 4) {
+    if (process == 0) sample_rad32(lt.cdf, a.tab.cdf[0], chi, k, v, omv);
+    else sample_pair32(lt.cdf, a.tab.cdf[1], chi, k, v, omv);
+  } else {
+    if (process == 0) sample_rad64(a.tab.cdf[0], chi, k, v, omv);
+    else sample_pair64(a.tab.cdf[1], chi, k, v, omv);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void advance_lepton(const StepArgs<T>& a, Lane<T>& L, T q, T h) {
+  if (a.push) boris<T>(L.p, q, L.E, L.B, h);
+  if (a.positions) {
+    const T gi = T(1) / sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
+    L.x[0] += L.p[0] * gi * h;
+    L.x[1] += L.p[1] * gi * h;
+    L.x[2] += L.p[2] * gi * h;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void write_child(const SpeciesView<T>& o, int64_t idx, const T p[3], const T x[3],
+                                            bool positions, float w, double tau, uint64_t id, uint32_t root, T tb) {
+  o.px[idx] = p[0];
+  o.py[idx] = p[1];
+  o.pz[idx] = p[2];
+  if (positions) {
+    o.x[idx] = x[0];
+    o.y[idx] = x[1];
+    o.z[idx] = x[2];
+  }
+  o.w[idx] = w;
+  o.tau[idx] = tau;
+  o.id[idx] = id;
+  o.root[idx] = root;
+  o.tb[idx] = tb;
+  if (o.alive) o.alive[idx] = 1;
+  if (o.nev) o.nev[idx] = 0;
+}
+
+// One sub-cycle of Algorithm 1 for a lepton.  Returns true when the particle
+// has reached the end of the step.
+template <typename T, bool kWrite>
+__device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTables& lt, Lane<T>& L, T q,
+                                            int64_t out_base) {
+  const T dtT = (T)a.dt;
+  if (!(L.t < dtT)) return true;
+  const T g = sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
+  T W = T(0);
+  if (a.emission && !L.capped && (double)g >= a.gamma_min) W = rate_of<T>(a, lt, 0, chi_of<T>(L.p, g, L.E, L.B), g);
+  const T rem = dtT - L.t;
+  const double X = (double)W * (double)rem;
+  if (!(W > T(0)) || L.tau > X) {  // no event before the end of the step
+    L.tau -= X;
+    advance_lepton<T>(a, L, q, rem);
+    L.t = dtT;
+    return true;
+  }
+  T h = (T)L.tau / W;  // the optical depth runs out after h
+  if (h > rem) h = rem;
+  advance_lepton<T>(a, L, q, h);
+  L.t += h;
+  const uint4 u = draw(a.seed, L.id, a.step, (uint32_t)L.j);
+  const T g2 = sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
+  const T chi_e = chi_of<T>(L.p, g2, L.E, L.B);  // the particle as it is at the event
+  T d, omd;
+  sample_of<T>(a, lt, 0, chi_e, u.x, d, omd);
+  if (kWrite) {
+    const int64_t o = out_base + L.j;
+    if (o < a.out_cap) {
+      const uint4 v = draw(a.seed, L.id, a.step, (uint32_t)L.j | 0x80000000u);
+      const T k[3] = {d * L.p[0], d * L.p[1], d * L.p[2]};
+      write_child<T>(a.out[0], o, k, L.x, a.positions, L.w, exp_depth(u.z),
+                     (uint64_t)v.x | ((uint64_t)v.y << 32), L.root, L.t);
+    }
+  }
+  L.p[0] *= omd;  // collinear recoil: photon k = delta p, lepton (1 - delta) p
+  L.p[1] *= omd;
+  L.p[2] *= omd;
+  L.tau = exp_depth(u.y);
+  ++L.j;
+  if (L.j >= a.max_events) L.capped = true;
+  return false;
+}
+
+// The photon counterpart: pair rate, straight-line motion, removed at its
+// first event (the pair takes xi and 1 - xi of its momentum).
+template <typename T, bool kWrite>
+__device__ __forceinline__ bool photon_iter(const StepArgs<T>& a, const LdsTables& lt, Lane<T>& L,
+                                            int64_t out_base) {
+  const T dtT = (T)a.dt;
+  if (!(L.t < dtT)) return true;
+  const T eps = sqrt(L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
+  T W = T(0);
+  if (a.pair && eps >= T(2)) W = rate_of<T>(a, lt, 1, chi_of<T>(L.p, eps, L.E, L.B), eps);
+  const T rem = dtT - L.t;
+  const double X = (double)W * (double)rem;
+  const T inv_eps = eps > T(0) ? T(1) / eps : T(0);
+  if (!(W > T(0)) || L.tau > X) {
+    L.tau -= X;
+    if (a.positions) {
+      L.x[0] += L.p[0] * inv_eps * rem;
+      L.x[1] += L.p[1] * inv_eps * rem;
+      L.x[2] += L.p[2] * inv_eps * rem;
+    }
+    L.t = dtT;
+    return true;
+  }
+  T h = (T)L.tau / W;
+  if (h > rem) h = rem;
+  if (a.positions) {
+    L.x[0] += L.p[0] * inv_eps * h;
+    L.x[1] += L.p[1] * inv_eps * h;
+    L.x[2] += L.p[2] * inv_eps * h;
+  }
+  L.t += h;
+  if (kWrite) {
+    const uint4 u = draw(a.seed, L.id, a.step, 0u);
+    const T chi = chi_of<T>(L.p, eps, L.E, L.B);
+    T xi, omx;
+    sample_of<T>(a, lt, 1, chi, u.x, xi, omx);
+    const int64_t o = out_base;
+    if (o < a.out_cap) {
+      const uint4 v = draw(a.seed, L.id, a.step, 0x80000000u);
+      const T pe[3] = {xi * L.p[0], xi * L.p[1], xi * L.p[2]};
+      const T pp[3] = {omx * L.p[0], omx * L.p[1], omx * L.p[2]};
+      write_child<T>(a.out[0], o, pe, L.x, a.positions, L.w, exp_depth(u.z), (uint64_t)v.x | ((uint64_t)v.y << 32),
+                     L.root, L.t);
+      write_child<T>(a.out[1], o, pp, L.x, a.positions, L.w, exp_depth(u.w), (uint64_t)v.z | ((uint64_t)v.w << 32),
+                     L.root, L.t);
+    }
+  }
+  L.j = 1;
+  return true;
+}
+
+template <typename T, bool kPhoton>
+__device__ __forceinline__ LdsTables stage_tables(const StepArgs<T>& a, float* lds) {
+  LdsTables lt{nullptr, nullptr};
+  if constexpr (sizeof(T) == 4) {
+    const int p = kPhoton ? 1 : 0;
+    const RateView& r = a.tab.rate[p];
+    const CdfView& c = a.tab.cdf[p];
+    float2* h = reinterpret_cast<float2*>(lds);
+    float* cdf = lds + 2 * r.n;
+    for (int i = threadIdx.x; i < r.n; i += blockDim.x) h[i] = r.herm[i];
+    const int nc = c.rows32 * c.cols32;
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) cdf[i] = c.f32[i];
+    lt.herm = h;
+    lt.cdf = cdf;
+  }
+  __syncthreads();
+  return lt;
+}
+
+// ------------------------------------------------------------------ count kernel
+template <typename T, bool kPhoton>
+__global__ void __launch_bounds__(kStepThreads) k_count(StepArgs<T> a) {
+  extern __shared__ float lds[];
+  const LdsTables lt = stage_tables<T, kPhoton>(a, lds);
+  const int64_t n = a.n;
+  const T q = a.species == 0 ? T(-1) : T(1);
+  Lane<T> L;
+  bool have = false, more = true;
+  int32_t local_max = 0;
+  bool capped = false;
+  while (true) {
+    const bool need = !have && more;
+    const uint64_t m = __ballot(need);
+    if (m) {
+      const int leader = __builtin_ctzll(m);
+      uint64_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(&a.queue[0], (unsigned long long)__popcll(m));
+      base = readlane64(base, leader);
+      if (base + (uint64_t)__popcll(m) >= (uint64_t)n) more = false;
+      if (need) {
+        const uint64_t k = base + mbcnt(m);
+        if (k < (uint64_t)n) {
+          load_lane<T>(a, (int64_t)k, L);
+          have = true;
+        }
+      }
+    }
+    if (!__any(have)) break;
+    if (have) {
+      const bool fin = kPhoton ? photon_iter<T, false>(a, lt, L, 0) : lepton_iter<T, false>(a, lt, L, q, 0);
+      if (fin) {
+        const int64_t i = a.begin + L.k;
+        a.counts[L.k] = L.j;
+        if (a.src.nev) a.src.nev[i] = L.j;
+        if (L.j == 0) store_final<T>(a, L, !kPhoton && a.push);
+        local_max = L.j > local_max ? L.j : local_max;
+        capped |= L.capped;
+        have = false;
+      }
+    }
+  }
+  // wave max of the event counts
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t o = __shfl_xor(local_max, off);
+    local_max = o > local_max ? o : local_max;
+  }
+  if (lane_id() == 0 && local_max > 0) atomicMax(&a.stats[kStatMaxEvents], (unsigned long long)local_max);
+  if (__any(capped) && lane_id() == 0) atomicOr(&a.stats[kStatCapped], 1ull);
+}
+
+// ------------------------------------------------------------------ scan kernel
+__global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
+  __shared__ int64_t sc[kScanThreads / 64];
+  __shared__ int32_t sf[kScanThreads / 64];
+  __shared__ int64_t s_tile, s_base_c, s_base_f;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_tile = (int64_t)atomicAdd(s.ticket, 1ull);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t k0 = tile * kScanTile + (int64_t)tid * kScanItems;
+  int32_t c[kScanItems];
+  int64_t my_c = 0;
+  int32_t my_f = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t k = k0 + i;
+    c[i] = k < s.n ? s.counts[k] : 0;
+    my_c += c[i];
+    my_f += c[i] > 0;
+  }
+  // wave-inclusive scans
+  int64_t ic = my_c;
+  int32_t inf = my_f;
+  const int lane = lane_id();
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t oc = __shfl_up(ic, off);
+    const int32_t of = __shfl_up(inf, off);
+    if (lane >= off) {
+      ic += oc;
+      inf += of;
+    }
+  }
+  const int wave = tid >> 6;
+  if (lane == 63) {
+    sc[wave] = ic;
+    sf[wave] = inf;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int64_t acc_c = 0;
+    int32_t acc_f = 0;
+    for (int wv = 0; wv < kScanThreads / 64; ++wv) {
+      const int64_t tc = sc[wv];
+      const int32_t tf = sf[wv];
+      sc[wv] = acc_c;
+      sf[wv] = acc_f;
+      acc_c += tc;
+      acc_f += tf;
+    }
+    const int64_t base = tile == 0 ? *s.cursor : 0;
+    s_base_c = lookback(s.state_c, tile, acc_c, base, s.epoch);
+    s_base_f = lookback(s.state_f, tile, acc_f, 0, s.epoch);
+    if (tile == s.num_tiles - 1) {
+      *s.cursor = s_base_c + acc_c;
+      *s.list_len = s_base_f + acc_f;
+    }
+  }
+  __syncthreads();
+  int64_t oc = s_base_c + sc[wave] + ic - my_c;
+  int32_t of = (int32_t)(s_base_f + sf[wave] + inf - my_f);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t k = k0 + i;
+    if (k < s.n) {
+      s.offsets[k] = oc;
+      if (c[i] > 0) s.list[of++] = (int32_t)k;
+    }
+    oc += c[i];
+  }
+}
+
+// ------------------------------------------------------------------ write kernel
+template <typename T, bool kPhoton>
+__global__ void __launch_bounds__(kStepThreads) k_write(StepArgs<T> a) {
+  extern __shared__ float lds[];
+  const LdsTables lt = stage_tables<T, kPhoton>(a, lds);
+  const int64_t n = *a.list_len;
+  const T q = a.species == 0 ? T(-1) : T(1);
+  Lane<T> L;
+  int64_t obase = 0;
+  bool have = false, more = n > 0;
+  while (true) {
+    const bool need = !have && more;
+    const uint64_t m = __ballot(need);
+    if (m) {
+      const int leader = __builtin_ctzll(m);
+      uint64_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(&a.queue[1], (unsigned long long)__popcll(m));
+      base = readlane64(base, leader);
+      if (base + (uint64_t)__popcll(m) >= (uint64_t)n) more = false;
+      if (need) {
+        const uint64_t e = base + mbcnt(m);
+        if (e < (uint64_t)n) {
+          const int64_t k = a.list[e];
+          load_lane<T>(a, k, L);
+          obase = a.offsets[k];
+          have = true;
+        }
+      }
+    }
+    if (!__any(have)) break;
+    if (have) {
+      const bool fin = kPhoton ? photon_iter<T, true>(a, lt, L, obase) : lepton_iter<T, true>(a, lt, L, q, obase);
+      if (fin) {
+        if (kPhoton) {
+          const int64_t i = a.begin + L.k;
+          if (a.positions) {
+            a.src.x[i] = L.x[0];
+            a.src.y[i] = L.x[1];
+            a.src.z[i] = L.x[2];
+          }
+          a.src.alive[i] = 0;
+        } else {
+          store_final<T>(a, L, true);
+        }
+        have = false;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ optical depth of new particles
+template <typename T>
+__global__ void k_init_tau(double* tau, const uint64_t* id, int64_t n, uint64_t seed, uint32_t step) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (tau[i] < 0.0) tau[i] = exp_depth(draw(seed, id[i], step, 0xFFFFFFFFu).x);
+}
+
+// ------------------------------------------------------------------ validation kernels
+template <typename T>
+__global__ void k_eval_rate(TableView tab, int process, const T* chi, const T* energy, T* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if constexpr (sizeof(T) == 4) {
+    const RateView& r = tab.rate[process];
+    out[i] = process == 0 ? rate_rad32(r.herm, r.n, r.hs_lo, r.inv_h, chi[i], energy[i])
+                          : rate_pair32(r.herm, r.n, r.hs_lo, r.inv_h, chi[i], energy[i]);
+  } else {
+    out[i] = process == 0 ? rate_rad64(tab.rate[0], chi[i], energy[i]) : rate_pair64(tab.rate[1], chi[i], energy[i]);
+  }
+}
+
+template <typename T>
+__global__ void k_eval_particles(TableView tab, int species, const T* px, const T* py, const T* pz, FieldView<T> f,
+                                 int64_t n, T* chi_out, T* w_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T p[3] = {px[i], py[i], pz[i]};
+  const int64_t o = f.stride ? i : 0;
+  const T E[3] = {f.ex[o], f.ey[o], f.ez[o]}, B[3] = {f.bx[o], f.by[o], f.bz[o]};
+  const T pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  const T e = species == 2 ? sqrt(pp) : sqrt(T(1) + pp);
+  const T chi = chi_of<T>(p, e, E, B);
+  T w;
+  if constexpr (sizeof(T) == 4) {
+    const RateView& r = tab.rate[species == 2 ? 1 : 0];
+    w = species == 2 ? (e >= 2.f ? rate_pair32(r.herm, r.n, r.hs_lo, r.inv_h, chi, e) : 0.f)
+                     : rate_rad32(r.herm, r.n, r.hs_lo, r.inv_h, chi, e);
+  } else {
+    w = species == 2 ? (e >= 2.0 ? rate_pair64(tab.rate[1], chi, e) : 0.0) : rate_rad64(tab.rate[0], chi, e);
+  }
+  if (chi_out) chi_out[i] = chi;
+  if (w_out) w_out[i] = w;
+}
+
+template <typename T>
+__global__ void k_sample(TableView tab, int process, const T* chi, const uint32_t* k, T* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T v, omv;
+  if constexpr (sizeof(T) == 4) {
+    if (process == 0) sample_rad32(tab.cdf[0].f32, tab.cdf[0], chi[i], k[i], v, omv);
+    else sample_pair32(tab.cdf[1].f32, tab.cdf[1], chi[i], k[i], v, omv);
+  } else {
+    if (process == 0) sample_rad64(tab.cdf[0], chi[i], k[i], v, omv);
+    else sample_pair64(tab.cdf[1], chi[i], k[i], v, omv);
+  }
+  out[i] = v;
+}
+
+// ------------------------------------------------------------------ merge
+// Stable compaction of photons (alive != 0) over the virtual sequence
+// main[0, n_main) ++ app[0, n_app) into main.  Each tile loads all its fields
+// before publishing its aggregate, so writes of later tiles never overwrite
+// elements that are still to be read (the destination index of an element is
+// never above its source index within main).
+template <typename T>
+__global__ void __launch_bounds__(kMergeThreads) k_merge_photons(MergeArgs<T> a) {
+  __shared__ int32_t wsum[kMergeThreads / 64];
+  __shared__ int64_t s_tile, s_base;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1ull);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t g = tile * kMergeThreads + tid;
+  const int64_t ntot = a.n_main + a.n_app;
+  bool ok = false;
+  T p[3] = {T(0), T(0), T(0)}, x[3] = {T(0), T(0), T(0)};
+  float w = 0.f;
+  double tau = 0.0;
+  uint64_t id = 0;
+  if (g < ntot) {
+    const bool in_main = g < a.n_main;
+    const SpeciesView<T>& s = in_main ? a.main : a.app;
+    const int64_t i = in_main ? g : g - a.n_main;
+    ok = s.alive[i] != 0;
+    if (ok) {
+      p[0] = s.px[i];
+      p[1] = s.py[i];
+      p[2] = s.pz[i];
+      if (a.positions) {
+        x[0] = s.x[i];
+        x[1] = s.y[i];
+        x[2] = s.z[i];
+      }
+      w = s.w[i];
+      tau = s.tau[i];
+      id = s.id[i];
+    }
+  }
+  const uint64_t m = __ballot(ok);
+  const int lane = lane_id(), wave = tid >> 6;
+  if (lane == 0) wsum[wave] = __popcll(m);
+  __syncthreads();
+  if (tid == 0) {
+    int32_t acc = 0;
+    for (int wv = 0; wv < kMergeThreads / 64; ++wv) {
+      const int32_t t = wsum[wv];
+      wsum[wv] = acc;
+      acc += t;
+    }
+    s_base = lookback(a.state, tile, acc, 0, a.epoch);
+    if (tile == a.num_tiles - 1) *a.out_count = s_base + acc;
+  }
+  __syncthreads();
+  if (ok) {
+    const int64_t o = s_base + wsum[wave] + mbcnt(m);
+    const SpeciesView<T>& d = a.main;
+    d.px[o] = p[0];
+    d.py[o] = p[1];
+    d.pz[o] = p[2];
+    if (a.positions) {
+      d.x[o] = x[0];
+      d.y[o] = x[1];
+      d.z[o] = x[2];
+    }
+    d.w[o] = w;
+    d.tau[o] = tau;
+    d.id[o] = id;
+    d.alive[o] = 1;
+  }
+}
+
+__global__ void k_count_alive(const uint8_t* a, int64_t n, unsigned long long* out) {
+  int64_t c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += a[i] != 0;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+// ------------------------------------------------------------------ explicit instantiations via launchers
+template <typename T, bool kPhoton>
+hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_count<T, kPhoton>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_count<T, kPhoton>), dim3(grid), dim3(kStepThreads), lds, st, a);
+  return hipGetLastError();
+}
+template <typename T, bool kPhoton>
+hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_write<T, kPhoton>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_write<T, kPhoton>), dim3(grid), dim3(kStepThreads), lds, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_scan(const ScanArgs& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3((unsigned)s.num_tiles), dim3(kScanThreads), 0, st, s);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_merge_photons(const MergeArgs<T>& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_merge_photons<T>), dim3((unsigned)a.num_tiles), dim3(kMergeThreads), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_count_alive(const uint8_t* alive, int64_t n, unsigned long long* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int grid = (int)((n + 255) / 256);
+  grid = grid > 4096 ? 4096 : grid;
+  hipLaunchKernelGGL(k_count_alive, dim3(grid), dim3(256), 0, st, alive, n, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_init_tau(double* tau, const uint64_t* id, int64_t n, uint64_t seed, uint32_t step, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_tau<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tau, id, n, seed, step);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_eval_rate(const TableView& tab, int process, const T* chi, const T* e, T* out, int64_t n,
+                            hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eval_rate<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tab, process, chi, e, out,
+                     n);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_eval_particles(const TableView& tab, int species, const T* px, const T* py, const T* pz,
+                                 const FieldView<T>& f, int64_t n, T* chi, T* w, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eval_particles<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tab, species, px, py,
+                     pz, f, n, chi, w);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_sample(const TableView& tab, int process, const T* chi, const uint32_t* k, T* out, int64_t n,
+                         hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tab, process, chi, k, out, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_count<float, false>(const StepArgs<float>&, int, size_t, hipStream_t);
+template hipError_t launch_count<float, true>(const StepArgs<float>&, int, size_t, hipStream_t);
+template hipError_t launch_count<double, false>(const StepArgs<double>&, int, size_t, hipStream_t);
+template hipError_t launch_count<double, true>(const StepArgs<double>&, int, size_t, hipStream_t);
+template hipError_t launch_write<float, false>(const StepArgs<float>&, int, size_t, hipStream_t);
+template hipError_t launch_write<float, true>(const StepArgs<float>&, int, size_t, hipStream_t);
+template hipError_t launch_write<double, false>(const StepArgs<double>&, int, size_t, hipStream_t);
+template hipError_t launch_write<double, true>(const StepArgs<double>&, int, size_t, hipStream_t);
+template hipError_t launch_merge_photons<float>(const MergeArgs<float>&, hipStream_t);
+template hipError_t launch_merge_photons<double>(const MergeArgs<double>&, hipStream_t);
+template hipError_t launch_init_tau<float>(double*, const uint64_t*, int64_t, uint64_t, uint32_t, hipStream_t);
+template hipError_t launch_eval_rate<float>(const TableView&, int, const float*, const float*, float*, int64_t,
+                                            hipStream_t);
+template hipError_t launch_eval_rate<double>(const TableView&, int, const double*, const double*, double*, int64_t,
+                                             hipStream_t);
+template hipError_t launch_eval_particles<float>(const TableView&, int, const float*, const float*, const float*,
+                                                 const FieldView<float>&, int64_t, float*, float*, hipStream_t);
+template hipError_t launch_eval_particles<double>(const TableView&, int, const double*, const double*, const double*,
+                                                  const FieldView<double>&, int64_t, double*, double*, hipStream_t);
+template hipError_t launch_sample<float>(const TableView&, int, const float*, const uint32_t*, float*, int64_t,
+                                         hipStream_t);
+template hipError_t launch_sample<double>(const TableView&, int, const double*, const uint32_t*, double*, int64_t,
+                                          hipStream_t);
+
+}  // namespace sfqed

@@ -1,0 +1,264 @@
+"""GPU parity of the step (Algorithms 1 and 2) against the FP64 oracle.
+
+Counts of events per particle must be identical except for decision flips
+(a particle whose event count differs; its subtree is excluded); the flip
+fraction must stay <= 1e-5 on the full 1e5-electron workload.  Children are
+matched by id (ids derive from ancestry and the draw counter), and their
+order in the append buffer must equal the oracle's wherever no flip shifts it.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import cast_inputs, compare_species, need_gpu, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch, sf = need_gpu()
+    return torch, sf, sf.Tables()
+
+
+def _emission_parity(env, n_idx, dtype_name, rtol_p):
+    torch, sf, tabs = env
+    dtype = getattr(torch, dtype_name)
+    np_dtype = np.float32 if dtype_name == "float32" else np.float64
+    wl = synth.emission_static_b(100_000, indices=n_idx)
+    inp = cast_inputs(wl, np_dtype)
+    n = inp[0]["id"].size
+    cap = [1, 1, n * 40]
+    cfg = sf.step_cfg(pair=False, push=False)
+    rc, st, gm, _, ga = run_gpu(sf, torch, tabs, wl, inp, dtype, cap, cfg)
+    assert rc == 0, rc
+    orc_rc, ost, om, oa = run_oracle(wl, inp, cap, emission=1, pair=0, push=0)
+    assert orc_rc == 0
+    g = gm[0].host()
+    nev_o = om[0].nev[:n]
+    flips = np.nonzero(g["nev"] != nev_o)[0]
+    print(f"{dtype_name} n={n}: events gpu {st.n_emit} oracle {ost.n_emit}, flips {flips.size}")
+    ok = g["nev"] == nev_o
+    err = np.linalg.norm(g["p"][ok] - om[0].p[ok], axis=1) / np.linalg.norm(om[0].p[ok], axis=1)
+    print(f"  parent momenta: max rel err {err.max():.2e} median {np.median(err):.2e}")
+    assert err.max() < rtol_p
+    # children: in order, parent blocks aligned by the scan of the counts
+    gc = ga[2].host()
+    off_g = np.r_[0, np.cumsum(g["nev"])]
+    off_o = np.r_[0, np.cumsum(nev_o)]
+    assert ga[2].count == off_g[-1] and oa[2].count == off_o[-1]
+    sel_g = np.concatenate([np.arange(off_g[i], off_g[i + 1]) for i in np.nonzero(ok)[0]])
+    sel_o = np.concatenate([np.arange(off_o[i], off_o[i + 1]) for i in np.nonzero(ok)[0]])
+    assert np.array_equal(gc["id"][sel_g], oa[2].id[sel_o])
+    assert np.array_equal(gc["root"][sel_g] & 0x3FFFFFFF, oa[2].root[sel_o].view(np.uint32) & 0x3FFFFFFF)
+    ke = np.linalg.norm(gc["p"][sel_g] - oa[2].p[sel_o], axis=1) / np.linalg.norm(oa[2].p[sel_o], axis=1)
+    te = np.abs(gc["t_birth"][sel_g] - oa[2].t_birth[sel_o]) / wl.dt
+    tau_e = np.abs(gc["tau"][sel_g] - oa[2].tau[sel_o])
+    print(f"  photons: max rel err k {ke.max():.2e}, t_birth/dt {te.max():.2e}, tau {tau_e.max():.2e}")
+    return flips.size, n, ke, te, tau_e
+
+
+def test_emission_fp64_parity(env):
+    idx = np.arange(0, 100_000, 23)  # 4348 particles: several blocks and a ragged tail
+    flips, n, ke, te, tau_e = _emission_parity(env, idx, "float64", 1e-6)
+    assert flips == 0
+    # photon energies carry the FP64 sampler's ~1e-8; later event times inherit it through chi
+    assert ke.max() < 1e-6 and te.max() < 1e-7 and tau_e.max() < 1e-12
+
+
+def test_emission_fp32_parity(env):
+    idx = np.arange(0, 100_000, 23)
+    flips, n, ke, te, tau_e = _emission_parity(env, idx, "float32", 2e-4)
+    assert flips <= max(1, int(1e-5 * n) + 1)
+    assert np.median(ke) < 1e-5
+
+
+@pytest.mark.slow
+def test_emission_fp32_full_flip_fraction(env):
+    """The full 1e5-electron workload: flip fraction <= 1e-5."""
+    flips, n, ke, te, tau_e = _emission_parity(env, None, "float32", 1e-3)
+    assert flips / n <= 1e-5
+
+
+def test_determinism_and_grid_independence(env):
+    torch, sf, tabs = env
+    wl = synth.emission_static_b(100_000, indices=np.arange(0, 100_000, 37))
+    inp = cast_inputs(wl, np.float32)
+    cap = [1, 1, 200_000]
+    cfg = sf.step_cfg(pair=False, push=False)
+    outs = []
+    for _ in range(2):
+        rc, st, gm, _, ga = run_gpu(sf, torch, tabs, wl, inp, torch.float32, cap, cfg)
+        outs.append((gm[0].host(), ga[2].host()))
+    for a, b in zip(outs[0], outs[1]):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+
+
+# ----------------------------------------------------------------------------- cascades with pairs
+def _match_all(ga_host, oa, gm_host, om):
+    """Match every particle (input and appended) by id; return per-species index pairs."""
+    out = []
+    for s in range(3):
+        g_ids = np.concatenate([gm_host[s]["id"], ga_host[s]["id"]])
+        o_ids = np.concatenate([om[s].id[:om[s].count], oa[s].id[:oa[s].count]])
+        pos = {int(v): i for i, v in enumerate(o_ids)}
+        ig = np.array([i for i, v in enumerate(g_ids) if int(v) in pos], dtype=np.int64)
+        io = np.array([pos[int(g_ids[i])] for i in ig], dtype=np.int64)
+        out.append((ig, io, g_ids.size, o_ids.size))
+    return out
+
+
+def _cascade(env, dtype_name, stride, push=False, dt_scale=1.0):
+    torch, sf, tabs = env
+    dtype = getattr(torch, dtype_name)
+    np_dtype = np.float32 if dtype_name == "float32" else np.float64
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, stride)] * 2 +
+                             [np.arange(0, 2_000_000, stride // 2)])
+    wl.dt *= dt_scale
+    inp = cast_inputs(wl, np_dtype)
+    n = sum(d["id"].size for d in inp)
+    cap = [n * 30, n * 30, n * 200]
+    cfg = sf.step_cfg(push=push, gamma_min=2.0)
+    rc, st, gm, _, ga = run_gpu(sf, torch, tabs, wl, inp, dtype, cap, cfg)
+    assert rc == 0, rc
+    orc_rc, ost, om, oa = run_oracle(wl, inp, cap, emission=1, pair=1, push=int(push), gamma_min=2.0)
+    assert orc_rc == 0
+    print(f"{dtype_name} push={push} n={n}: gpu emit {st.n_emit} pair {st.n_pair} rounds {st.n_rounds}; "
+          f"oracle emit {ost.n_emit} pair {ost.n_pair} rounds {ost.n_rounds}")
+    gmh = [m.host() for m in gm]
+    gah = [a.host() for a in ga]
+    return wl, st, ost, gmh, gah, om, oa
+
+
+def _cat(h, om_or_oa_main, om_or_oa_app, key):
+    return np.concatenate([om_or_oa_main, om_or_oa_app])
+
+
+def test_cascade_fp64_parity(env):
+    wl, st, ost, gmh, gah, om, oa = _cascade(env, "float64", 20_000)
+    assert st.n_pair > 0 and st.n_rounds >= 3
+    # no flips expected in FP64: every count and every record in the same order
+    assert (st.n_emit, st.n_pair, st.n_rounds) == (ost.n_emit, ost.n_pair, ost.n_rounds)
+    for s in range(3):
+        assert np.array_equal(gmh[s]["nev"], om[s].nev[:om[s].count])
+        assert np.array_equal(gah[s]["id"], oa[s].id[:oa[s].count])
+        assert np.array_equal(gah[s]["nev"], oa[s].nev[:oa[s].count])
+        if s == 2:
+            assert np.array_equal(gah[s]["alive"], oa[s].alive[:oa[s].count])
+            assert np.array_equal(gmh[s]["alive"], om[s].alive[:om[s].count])
+        err = np.linalg.norm(gah[s]["p"] - oa[s].p, axis=1) / np.maximum(np.linalg.norm(oa[s].p, axis=1), 1e-300)
+        print(f"  species {s}: {gah[s]['id'].size} appended, max rel err p {err.max() if err.size else 0:.2e}")
+        assert err.size == 0 or err.max() < 1e-6
+
+
+def test_cascade_fp32_parity(env):
+    wl, st, ost, gmh, gah, om, oa = _cascade(env, "float32", 20_000)
+    m = _match_all(gah, oa, gmh, om)
+    flips = tot = 0
+    for s in range(3):
+        ig, io, ng, no = m[s]
+        g_nev = np.concatenate([gmh[s]["nev"], gah[s]["nev"]])[ig]
+        o_nev = np.concatenate([om[s].nev[:om[s].count], oa[s].nev[:oa[s].count]])[io]
+        flips += int((g_nev != o_nev).sum())
+        tot += ig.size
+        print(f"  species {s}: gpu {ng} oracle {no} matched {ig.size}")
+    print(f"  flip fraction {flips / tot:.2e} ({flips} of {tot})")
+    assert flips / tot < 1e-3
+    assert abs(st.n_emit - ost.n_emit) <= 0.01 * ost.n_emit
+
+
+def test_push_fp64_parity(env):
+    """Boris push between events (rotating-field workload, one short step)."""
+    torch, sf, tabs = env
+    wl = synth.rotating_e(1_000_000, indices=np.arange(0, 1_000_000, 997), dt=300.0)
+    inp = cast_inputs(wl, np.float64)
+    n = inp[0]["id"].size
+    cap = [n * 20, n * 20, n * 100]
+    cfg = sf.step_cfg(push=True)
+    rc, st, gm, _, ga = run_gpu(sf, torch, tabs, wl, inp, torch.float64, cap, cfg)
+    assert rc == 0
+    orc_rc, ost, om, oa = run_oracle(wl, inp, cap, emission=1, pair=1, push=1)
+    print(f"push: gpu emit {st.n_emit} pair {st.n_pair}; oracle emit {ost.n_emit} pair {ost.n_pair}")
+    g = gm[0].host()
+    assert np.array_equal(g["nev"], om[0].nev[:n])
+    err = np.linalg.norm(g["p"] - om[0].p, axis=1) / np.linalg.norm(om[0].p, axis=1)
+    print(f"  max rel err of pushed momenta {err.max():.2e}")
+    assert err.max() < 1e-7
+    assert (st.n_emit, st.n_pair) == (ost.n_emit, ost.n_pair)
+
+
+def test_merge_parity(env, orc):
+    torch, sf, tabs = env
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 40_000)] * 2 +
+                             [np.arange(0, 2_000_000, 20_000)])
+    inp = cast_inputs(wl, np.float64)
+    n = sum(d["id"].size for d in inp)
+    cap = [n * 30, n * 30, n * 200]
+    cfg = sf.step_cfg(push=False, gamma_min=2.0)
+    rc, st, gm, gf, ga = run_gpu(sf, torch, tabs, wl, inp, torch.float64, cap, cfg)
+    assert rc == 0
+    orc_rc, ost, om, oa = run_oracle(wl, inp, cap, emission=1, pair=1, push=0, gamma_min=2.0)
+    # grow the main stores to hold the merged ensemble
+    big = []
+    for s in range(3):
+        h = gm[s].host()
+        b = sf.Store.from_arrays(h["p"], h["w"], h["tau"], h["id"], dtype=torch.float64, photon=s == 2,
+                                 capacity=gm[s].count + ga[s].count)
+        if s == 2:
+            b.alive[:gm[s].count] = gm[s].alive[:gm[s].count]
+        big.append(b)
+    sf.merge(big, gf, ga)
+    om2 = [orc.Store(om[s].count + oa[s].count) for s in range(3)]
+    for s in range(3):
+        c = om[s].count
+        om2[s].state[:c] = om[s].state[:c]
+        om2[s].id[:c] = om[s].id[:c]
+        om2[s].alive[:c] = om[s].alive[:c]
+        om2[s].count = c
+    assert orc.merge(om2, oa) == 0
+    for s in range(3):
+        h = big[s].host()
+        print(f"  species {s}: merged {big[s].count} (oracle {om2[s].count})")
+        assert big[s].count == om2[s].count
+        assert np.array_equal(h["id"], om2[s].id[:om2[s].count])
+        np.testing.assert_allclose(h["p"], om2[s].p, rtol=1e-6)
+
+
+def test_capacity_overflow(env):
+    torch, sf, tabs = env
+    wl = synth.emission_static_b(100_000, indices=np.arange(0, 100_000, 100))
+    inp = cast_inputs(wl, np.float32)
+    main = [sf.Store.from_arrays(inp[0]["p"], inp[0]["w"], inp[0]["tau"], inp[0]["id"], dtype=torch.float32),
+            sf.Store.empty(1, torch.float32), sf.Store.empty(1, torch.float32, photon=True)]
+    fields = [sf.Fields.from_array(inp[0]["fields"]), sf.Fields.from_array(np.zeros((1, 6))),
+              sf.Fields.from_array(np.zeros((1, 6)))]
+    app = [sf.Store.empty(4, torch.float32, append=True), sf.Store.empty(4, torch.float32, append=True),
+           sf.Store.empty(64, torch.float32, photon=True, append=True)]
+    app[2].px.fill_(12345.0)
+    app[2].cap = 50  # the library may use 50 of the 64 slots
+    rc, st = sf.step(tabs, main, fields, app, wl.dt, 0, 0, sf.step_cfg(pair=False, push=False), check=False)
+    torch.cuda.synchronize()
+    assert rc == 2, rc
+    print(f"overflow: required photons {st.required_capacity[2]} > capacity 50")
+    assert st.required_capacity[2] > 50
+    assert app[2].count == 50
+    assert torch.all(app[2].px[50:] == 12345.0)
+    assert not torch.any(app[2].px[:50] == 12345.0)
+
+
+def test_init_tau_parity(env, orc):
+    torch, sf, tabs = env
+    n = 1000
+    ids = np.arange(n, dtype=np.uint64) * 7919 + 3
+    tau = np.where(np.arange(n) % 3 == 0, 1.5, -1.0)
+    s = sf.Store.from_arrays(np.zeros((n, 3)), np.ones(n), tau, ids, dtype=torch.float32)
+    e = sf.Store.empty(0, torch.float32)
+    g = sf.Store.empty(0, torch.float32, photon=True)
+    z = sf.Fields.from_array(np.zeros((1, 6)))
+    sf.init_tau([s, e, g], [z, z, z], 77, 5)
+    got = s.tau[:n].cpu().numpy()
+    o = orc.Store.from_arrays(np.zeros((n, 3)), np.ones(n), tau, ids)
+    orc.init_tau(o, 77, 5)
+    np.testing.assert_allclose(got, o.tau, rtol=4e-16, atol=0)
+    assert np.array_equal(got[::3], tau[::3])
