@@ -1,0 +1,239 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the SFQED event generator on one MI355X.
+
+A step is one global time step of the crossed-field workload through the whole
+hot path: restore the 1e7-particle input ensemble into the working buffers
+(device copies), qed_step (chi, rates, optical-depth sub-cycling, inverse-CDF
+sampling, recoil, deterministic append, every generation of secondaries), and
+qed_merge (drop photons that made pairs, append the children).  Inputs are
+resident in HBM before timing starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "particle-steps/s + QED events/s on 1 GPU; surrogate vs table at fixed error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------------- algorithmic bytes
+def kernel_bytes(name: str, st: dict, n_main: list, n_step: int) -> float:
+    """Bytes the method must move in all launches of one kernel during n_step steps
+    (FP32 momenta/fields/times, FP64 optical depth, u64 ids; push off, no positions)."""
+    P = st["kernel_particles"]
+    ev_l, ev_p = st["event_particles"]
+    n_emit, n_pair = st["n_emit"], st["n_pair"]
+    main_l = (n_main[0] + n_main[1]) * n_step
+    main_p = n_main[2] * n_step
+    if name == "count_lepton":
+        # read p 12, E and B 24, tau 8, id 8 (+ root 4, t_birth 4 for children); write the
+        # count 4 and, for particles without events, tau 8
+        n = P[0]
+        return n * (52 + 4) + (n - main_l) * 8 + (n - ev_l) * 8
+    if name == "scan":
+        return P[1] * (4 + 8) + (ev_l + ev_p) * 4
+    if name == "write_lepton":
+        return ev_l * (52 + 4 + 8 + 4 + 12 + 8) + n_emit * 41
+    if name == "count_photon":
+        n = P[3]
+        return n * (52 + 4) + (n - main_p) * 8 + (n - ev_p) * 8
+    if name == "write_photon":
+        return ev_p * (52 + 4 + 8 + 4 + 1) + 2 * n_pair * 40
+    raise KeyError(name)
+
+
+# ----------------------------------------------------------------------------- workload on the device
+class DeviceWorkload:
+    def __init__(self, sf, torch, wl, caps, dtype):
+        self.sf, self.torch, self.wl, self.dtype = sf, torch, wl, dtype
+        self.n = [s.n for s in wl.species]
+        np_ = __import__("numpy")
+        self.pristine = []
+        self.main, self.fields, self.app = [], [], []
+        for s, sp in enumerate(wl.species):
+            pr = sf.Store.from_arrays(sp.p, sp.w, sp.tau, sp.id, dtype=dtype, photon=s == 2,
+                                      capacity=max(sp.n, 1))
+            self.pristine.append(pr)
+            self.fields.append(sf.Fields.from_array(sp.fields if sp.fields.shape[0] else np_.zeros((1, 6)), dtype))
+            self.main.append(sf.Store.empty(max(sp.n + caps[s], 1), dtype, photon=s == 2, nev=False))
+            self.app.append(sf.Store.empty(max(caps[s], 1), dtype, photon=s == 2, append=True, nev=False))
+
+    def restore(self):
+        for s in range(3):
+            n, src, dst = self.n[s], self.pristine[s], self.main[s]
+            for k in ("px", "py", "pz", "w", "tau", "id"):
+                getattr(dst, k)[:n].copy_(getattr(src, k)[:n])
+            if s == 2:
+                dst.alive[:n].fill_(1)
+            dst.count = n
+
+    def step(self, tables, index, cfg):
+        self.restore()
+        rc, st = self.sf.step(tables, self.main, self.fields, self.app, self.wl.dt, 0, index, cfg, check=False)
+        if rc != 0:
+            return rc, st
+        self.sf.merge(self.main, self.fields, self.app)
+        return 0, st
+
+
+def sum_stats(stats: list) -> dict:
+    out = {}
+    for st in stats:
+        d = st.as_dict()
+        for k, v in d.items():
+            if isinstance(v, list):
+                out[k] = [a + b for a, b in zip(out.get(k, [0] * len(v)), v)]
+            else:
+                out[k] = out.get(k, 0) + v
+    return out
+
+
+# ----------------------------------------------------------------------------- CPU baseline
+def cpu_baseline(wl_fn, full_n, stride, gamma_min):
+    """The FP64 oracle on a strided sample of the same workload (FP32-rounded inputs)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    counts = [int(round(full_n * 0.4)), int(round(full_n * 0.4))]
+    counts.append(full_n - sum(counts))
+    idx = [np.arange(0, counts[0], stride), np.arange(0, counts[1], stride), np.arange(0, counts[2], stride)]
+    wl = wl_fn(full_n, indices=idx)
+    main, fields = [], []
+    for sp in wl.species:
+        p = sp.p.astype(np.float32).astype(np.float64)
+        main.append(oracle.Store.from_arrays(p, sp.w, sp.tau, sp.id, capacity=max(sp.n, 1)))
+        fields.append(sp.fields.astype(np.float32).astype(np.float64))
+    n = sum(wl.counts)
+    app = [oracle.Store(n * 40), oracle.Store(n * 40), oracle.Store(n * 300)]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    rc, st = oracle.step(main, fields, app, wl.dt, 0, 0, emission=1, pair=1, push=0, gamma_min=gamma_min)
+    el = time.perf_counter() - t0
+    assert rc == 0, rc
+    return {"value": n / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th particle of each species ({n} particles, {st.n_emit + st.n_pair} events, "
+                      f"{el:.1f} s)", "events_per_s": (st.n_emit + st.n_pair) / el}
+
+
+# ----------------------------------------------------------------------------- main
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--cpu-stride", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--gamma-min", type=float, default=2.0)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the event generator runs on a single MI355X here "
+              "(a multi-GPU run would shard particles by index; see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2409_17299_amd as sf
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    log(f"generating the crossed-field workload ({args.n} particles)")
+    t0 = time.perf_counter()
+    wl = synth.crossed_field(args.n)
+    log(f"  generated in {time.perf_counter() - t0:.1f} s; dt = {wl.dt:.6g}")
+    tables = sf.Tables()
+    dtype = torch.float32
+    cfg = sf.step_cfg(push=False, gamma_min=args.gamma_min, profile=True)
+
+    # size the append buffers with one generous step
+    caps = [int(args.n * 12), int(args.n * 12), int(min(args.n * 100, (1 << 30) - 1024))]
+    while True:
+        dw = DeviceWorkload(sf, torch, wl, caps, dtype)
+        rc, st = dw.step(tables, 10_000, cfg)
+        if rc == 0:
+            break
+        if rc != 2:
+            raise sf.SfqedError(rc, "sizing step")
+        need = list(st.required_capacity)
+        log(f"  append capacity {caps} too small (needed at least {need}); growing")
+        caps = [int(min(max(c * 2, r * 1.3), (1 << 30) - 1024)) for c, r in zip(caps, need)]
+        del dw
+        torch.cuda.empty_cache()
+    caps = [int(min(max(r * 1.25, 1024), (1 << 30) - 1024)) for r in st.required_capacity]
+    del dw
+    torch.cuda.empty_cache()
+    dw = DeviceWorkload(sf, torch, wl, caps, dtype)
+    log(f"  capacities {caps}")
+
+    for i in range(args.warmup):
+        rc, st = dw.step(tables, i, cfg)
+        assert rc == 0, rc
+        log(f"warmup step {i}: {st.n_emit} photons, {st.n_pair} pairs, {st.n_rounds} rounds")
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        rc, st = dw.step(tables, args.warmup + i, cfg)
+        assert rc == 0, rc
+        stats.append(st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el * 1e3 / args.steps
+    S = sum_stats(stats)
+    log(f"timed: {args.steps} steps in {el:.3f} s ({ms:.2f} ms/step); per-kernel ms "
+        f"{dict(zip(sf.StepStats.KERNELS, [round(v / args.steps, 3) for v in S['kernel_ms']]))}")
+
+    n_particles = sum(dw.n)
+    events = (S["n_emit"] + S["n_pair"]) / args.steps
+    kern = {}
+    for k, name in enumerate(sf.StepStats.KERNELS):
+        if S["kernel_launches"][k] == 0:
+            continue
+        b = kernel_bytes(name, S, dw.n, args.steps)
+        kern[name] = {"ms_total": S["kernel_ms"][k], "launches": S["kernel_launches"][k],
+                      "avg_launch_ms": S["kernel_ms"][k] / S["kernel_launches"][k],
+                      "bytes": b, "gbs": b / (S["kernel_ms"][k] * 1e-3) / 1e9}
+    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    d = kern[dom]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(d["avg_launch_ms"], 4), "bytes_per_launch": d["bytes"] / d["launches"]}
+
+    out = {"metric": METRIC, "value": round(n_particles / (ms * 1e-3), 1), "unit": "particle-steps/s",
+           "events_per_s": round(events / (ms * 1e-3), 1), "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "crossed_field", "particles": n_particles, "electrons": dw.n[0],
+                      "positrons": dw.n[1], "photons": dw.n[2], "chi_range": [0.1, 100.0],
+                      "energy_range": [1e2, 1e4], "dt": wl.dt, "processes": "emission+pair", "push": False,
+                      "gamma_min": args.gamma_min, "precision": "fp32 particles/tables, fp64 optical depth",
+                      "events_per_step": events, "rounds": S["n_rounds"] / args.steps},
+           "roofline": roof,
+           "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                       for k, v in kern.items()}}
+    if not args.no_cpu:
+        log("CPU baseline: the FP64 oracle on a strided sample")
+        out["cpu_baseline"] = cpu_baseline(synth.crossed_field, args.n, args.cpu_stride, args.gamma_min)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -148,12 +148,13 @@ typedef struct {
   int64_t max_events;               /* largest number of events of one particle */
   int64_t required_capacity[3];     /* append sizes needed (lower bound on overflow) */
   int64_t n_launches;               /* particle-range launches (count, scan, write each) */
-  double ms_lepton, ms_photon;      /* summed kernel time of lepton / photon launches (profile = 1) */
-  double ms_lepton_main;            /* the lepton launches over the input ensemble */
-  double ms_count_main;             /* ... their count kernels only */
-  double ms_write_main;             /* ... their scan + write kernels */
-  int64_t n_lepton_main;            /* particles in those launches */
-  int64_t n_children_main;          /* photons they appended */
+  /* Per kernel, indexed 0 count (leptons), 1 scan, 2 write (leptons),
+   * 3 count (photons), 4 write (photons).  kernel_ms needs profile = 1 (HIP
+   * events on the step's stream, read after the step; no extra waits). */
+  double kernel_ms[5];
+  int64_t kernel_launches[5];
+  int64_t kernel_particles[5];      /* particles in the launches' ranges */
+  int64_t event_particles[2];       /* particles with events: leptons, photons */
 } qed_step_stats;
 
 /* Draws tau = -ln(u) for every particle with tau < 0 (u from Philox4x32-10,

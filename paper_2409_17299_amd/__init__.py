@@ -64,9 +64,10 @@ class StepCfg(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("n_emit", C.c_int64), ("n_pair", C.c_int64), ("n_new", C.c_int64 * 3), ("n_rounds", C.c_int64),
                 ("max_events", C.c_int64), ("required_capacity", C.c_int64 * 3), ("n_launches", C.c_int64),
-                ("ms_lepton", C.c_double), ("ms_photon", C.c_double), ("ms_lepton_main", C.c_double),
-                ("ms_count_main", C.c_double), ("ms_write_main", C.c_double), ("n_lepton_main", C.c_int64),
-                ("n_children_main", C.c_int64)]
+                ("kernel_ms", C.c_double * 5), ("kernel_launches", C.c_int64 * 5),
+                ("kernel_particles", C.c_int64 * 5), ("event_particles", C.c_int64 * 2)]
+
+    KERNELS = ("count_lepton", "scan", "write_lepton", "count_photon", "write_photon")
 
     def as_dict(self) -> dict:
         d = {}

@@ -61,15 +61,18 @@ Scratch* scratch_for_current_device() {
   Scratch* s = new Scratch();
   s->device = dev;
   int v = 0;
-  hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
   s->num_cu = v > 0 ? v : 1;
-  hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   s->max_lds = v > 0 ? (size_t)v : 65536;
   if (hipMalloc(&s->ctrl, sizeof(uint64_t) * kCtrlWords) != hipSuccess) {
     delete s;
     return nullptr;
   }
-  hipMemset(s->ctrl, 0, sizeof(uint64_t) * kCtrlWords);
+  if (hipMemset(s->ctrl, 0, sizeof(uint64_t) * kCtrlWords) != hipSuccess) {
+    delete s;
+    return nullptr;
+  }
   g_scratch.push_back(s);
   return s;
 }
@@ -79,9 +82,9 @@ qed_status ensure_scratch(Scratch* s, int64_t n) {
     const int64_t cap = std::max<int64_t>(n, s->cap * 3 / 2);
     if (s->counts) {
       SFQED_HIP(hipDeviceSynchronize());
-      hipFree(s->counts);
-      hipFree(s->offsets);
-      hipFree(s->list);
+      (void)hipFree(s->counts);
+      (void)hipFree(s->offsets);
+      (void)hipFree(s->list);
       s->counts = nullptr;
     }
     SFQED_HIP(hipMalloc(&s->counts, sizeof(int32_t) * cap));
@@ -93,8 +96,8 @@ qed_status ensure_scratch(Scratch* s, int64_t n) {
   if (tiles > s->tiles_cap) {
     if (s->state_c) {
       SFQED_HIP(hipDeviceSynchronize());
-      hipFree(s->state_c);
-      hipFree(s->state_f);
+      (void)hipFree(s->state_c);
+      (void)hipFree(s->state_f);
     }
     SFQED_HIP(hipMalloc(&s->state_c, sizeof(uint64_t) * tiles));
     SFQED_HIP(hipMalloc(&s->state_f, sizeof(uint64_t) * tiles));
@@ -165,42 +168,59 @@ bool fields_ok(const qed_fields& f, int64_t n) {
   return f.stride == 0 || f.stride == 1;
 }
 
-struct Timer {
-  bool on;
-  hipStream_t st;
-  hipEvent_t a, b;
-  Timer(bool on_, hipStream_t s) : on(on_), st(s) {
-    if (on) {
-      hipEventCreate(&a);
-      hipEventCreate(&b);
+// HIP events around kernels, read once the step has finished (no extra waits).
+struct EventLog {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
     }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
   }
-  ~Timer() {
-    if (on) {
-      hipEventDestroy(a);
-      hipEventDestroy(b);
+  hipEvent_t begin() {
+    if (!on) return nullptr;
+    hipEvent_t e = get();
+    if (e && hipEventRecord(e, st) != hipSuccess) return nullptr;
+    return e;
+  }
+  void end(int kind, hipEvent_t a) {
+    if (!on || !a) return;
+    hipEvent_t b = get();
+    if (b && hipEventRecord(b, st) == hipSuccess) marks.push_back({kind, {a, b}});
+  }
+  // after the stream has been synchronised
+  void collect(double* ms) {
+    for (auto& m : marks) {
+      float v = 0.f;
+      if (hipEventElapsedTime(&v, m.second.first, m.second.second) == hipSuccess) ms[m.first] += v;
+      pool.push_back(m.second.first);
+      pool.push_back(m.second.second);
     }
+    marks.clear();
   }
-  void start() {
-    if (on) hipEventRecord(a, st);
-  }
-  double stop() {
-    if (!on) return 0.0;
-    hipEventRecord(b, st);
-    hipEventSynchronize(b);
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, a, b);
-    return ms;
+  ~EventLog() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    for (auto& m : marks) {
+      (void)hipEventDestroy(m.second.first);
+      (void)hipEventDestroy(m.second.second);
+    }
   }
 };
 
 // One launch (count, scan, write) over particles [begin, begin + n) of one
-// store.  Returns the kernel time when profiling.
+// store.
 template <typename T>
 qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const qed_step_cfg* cfg,
                       const qed_ensemble* ens, qed_species* app, int species, bool from_main, int64_t begin,
-                      int64_t n, double dt, uint64_t seed, uint32_t step, int* slot, bool positions,
-                      double* ms_total, double* ms_count, double* ms_write) {
+                      int64_t n, double dt, uint64_t seed, uint32_t step, int* slot, bool positions, EventLog& log,
+                      qed_step_stats* stats) {
   if (n <= 0) return QED_OK;
   qed_status rc = ensure_scratch(S, n);
   if (rc != QED_OK) return rc;
@@ -251,9 +271,11 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
 
   const int p = photon ? 1 : 0;
   size_t lds = 0;
-  if (sizeof(T) == 4) lds = sizeof(float2) * tab->view.rate[p].n + sizeof(float) * tab->view.cdf[p].rows32 * tab->view.cdf[p].cols32;
-  const int per_cu = sizeof(T) == 4 ? std::max<int>(1, (int)(160 * 1024 / std::max<size_t>(lds, 1))) : 4;
-  const int max_grid = S->num_cu * std::min(per_cu, 2);
+  if (sizeof(T) == 4)
+    lds = sizeof(float2) * tab->view.rate[p].n +
+          sizeof(float) * tab->view.cdf[p].rows32 * tab->view.cdf[p].cols32;
+  // leptons: 2 blocks per CU (the emission tables take ~78 KiB of LDS); photons: 4
+  const int max_grid = S->num_cu * (photon ? 4 : 2);
   const int grid = (int)std::min<int64_t>((n + kStepThreads - 1) / kStepThreads, max_grid);
 
   ScanArgs s;
@@ -268,33 +290,35 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   s.epoch = next_epoch(S);
   s.ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot + 2);
   s.num_tiles = (n + kScanTile - 1) / kScanTile;
+  s.event_particles = reinterpret_cast<unsigned long long*>(S->ctrl + kStats + kStatEventParticles + p);
   *slot += 3;
 
-  const bool prof = cfg->profile != 0;
-  Timer t0(prof, st);
-  t0.start();
+  const int k_count = photon ? 3 : 0, k_write = photon ? 4 : 2;
+  hipEvent_t e0 = log.begin();
   hipError_t e = photon ? launch_count<T, true>(a, grid, lds, st) : launch_count<T, false>(a, grid, lds, st);
   if (e != hipSuccess) {
     set_error(std::string("count kernel: ") + hipGetErrorString(e));
     return QED_ERR_HIP;
   }
-  const double mc = t0.stop();
-  Timer t1(prof, st);
-  t1.start();
+  log.end(k_count, e0);
+  e0 = log.begin();
   e = launch_scan(s, st);
   if (e != hipSuccess) {
     set_error(std::string("scan kernel: ") + hipGetErrorString(e));
     return QED_ERR_HIP;
   }
+  log.end(1, e0);
+  e0 = log.begin();
   e = photon ? launch_write<T, true>(a, grid, lds, st) : launch_write<T, false>(a, grid, lds, st);
   if (e != hipSuccess) {
     set_error(std::string("write kernel: ") + hipGetErrorString(e));
     return QED_ERR_HIP;
   }
-  const double mw = t1.stop();
-  if (ms_total) *ms_total += mc + mw;
-  if (ms_count) *ms_count += mc;
-  if (ms_write) *ms_write += mw;
+  log.end(k_write, e0);
+  for (int k : {k_count, 1, k_write}) {
+    stats->kernel_launches[k] += 1;
+    stats->kernel_particles[k] += n;
+  }
   return QED_OK;
 }
 
@@ -322,30 +346,27 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
     return QED_OK;
   };
   const int64_t capg = app[2].capacity, capl = std::min(app[0].capacity, app[1].capacity);
-  double* ms_lep = &local.ms_lepton;
-  double* ms_pho = &local.ms_photon;
+  EventLog log;
+  log.on = cfg->profile != 0;
+  log.st = st;
   qed_status rc;
   int64_t launches = 0;
-  auto launch = [&](int species, bool from_main, int64_t begin, int64_t n, double* msa, double* msb,
-                    double* msc) -> qed_status {
+  auto launch = [&](int species, bool from_main, int64_t begin, int64_t n) -> qed_status {
     if (n <= 0) return QED_OK;
     ++launches;
     return run_launch<T>(S, st, tab, cfg, ens, app, species, from_main, begin, n, dt, seed, step, &slot, positions,
-                         msa, msb, msc);
+                         log, &local);
   };
   // round 0: the input ensemble, then the photons its leptons emitted
-  double ms_main = 0.0, ms_count_main = 0.0, ms_write_main = 0.0;
-  if ((rc = launch(0, true, 0, ens->s[0].count, &ms_main, &ms_count_main, &ms_write_main)) != QED_OK) return rc;
-  if ((rc = launch(1, true, 0, ens->s[1].count, &ms_main, &ms_count_main, &ms_write_main)) != QED_OK) return rc;
-  *ms_lep += ms_main;
+  if ((rc = launch(0, true, 0, ens->s[0].count)) != QED_OK) return rc;
+  if ((rc = launch(1, true, 0, ens->s[1].count)) != QED_OK) return rc;
   if ((rc = read_cursors()) != QED_OK) return rc;
-  local.n_children_main = cur[0];
   int64_t g_done = 0;
   bool overflow = cur[0] > capg;
   if (!overflow) {
-    if ((rc = launch(2, true, 0, ens->s[2].count, ms_pho, nullptr, nullptr)) != QED_OK) return rc;
+    if ((rc = launch(2, true, 0, ens->s[2].count)) != QED_OK) return rc;
     const int64_t g_hi = cur[0];
-    if ((rc = launch(2, false, 0, g_hi, ms_pho, nullptr, nullptr)) != QED_OK) return rc;
+    if ((rc = launch(2, false, 0, g_hi)) != QED_OK) return rc;
     g_done = g_hi;
     if ((rc = read_cursors()) != QED_OK) return rc;
     overflow = cur[0] > capg || cur[1] > capl;
@@ -353,8 +374,8 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   int64_t rounds = 1, l_done = 0;
   while (!overflow && cur[1] > l_done) {
     const int64_t l_hi = cur[1];
-    if ((rc = launch(0, false, l_done, l_hi - l_done, ms_lep, nullptr, nullptr)) != QED_OK) return rc;
-    if ((rc = launch(1, false, l_done, l_hi - l_done, ms_lep, nullptr, nullptr)) != QED_OK) return rc;
+    if ((rc = launch(0, false, l_done, l_hi - l_done)) != QED_OK) return rc;
+    if ((rc = launch(1, false, l_done, l_hi - l_done)) != QED_OK) return rc;
     l_done = l_hi;
     if ((rc = read_cursors()) != QED_OK) return rc;
     if (cur[0] > capg) {
@@ -362,7 +383,7 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
       break;
     }
     const int64_t g_hi = cur[0];
-    if ((rc = launch(2, false, g_done, g_hi - g_done, ms_pho, nullptr, nullptr)) != QED_OK) return rc;
+    if ((rc = launch(2, false, g_done, g_hi - g_done)) != QED_OK) return rc;
     g_done = g_hi;
     if ((rc = read_cursors()) != QED_OK) return rc;
     overflow = cur[0] > capg || cur[1] > capl;
@@ -382,10 +403,9 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   local.required_capacity[1] = cur[1];
   local.required_capacity[2] = cur[0];
   local.n_launches = launches;
-  local.ms_lepton_main = ms_main;
-  local.ms_count_main = ms_count_main;
-  local.ms_write_main = ms_write_main;
-  local.n_lepton_main = ens->s[0].count + ens->s[1].count;
+  local.event_particles[0] = (int64_t)dev_stats[kStatEventParticles];
+  local.event_particles[1] = (int64_t)dev_stats[kStatEventParticles + 1];
+  log.collect(local.kernel_ms);
   app[0].count = std::min(cur[1], app[0].capacity);
   app[1].count = std::min(cur[1], app[1].capacity);
   app[2].count = std::min(cur[0], app[2].capacity);
@@ -447,12 +467,12 @@ qed_status merge_impl(qed_ensemble* ens, const qed_species* app, hipStream_t st)
   if (ntot > 0) {
     qed_status rc = ensure_scratch(S, 1);
     if (rc != QED_OK) return rc;
-    const int64_t tiles = (ntot + kMergeThreads - 1) / kMergeThreads;
+    const int64_t tiles = (ntot + kMergeTile - 1) / kMergeTile;
     if (tiles > S->tiles_cap) {
       if (S->state_c) {
         SFQED_HIP(hipDeviceSynchronize());
-        hipFree(S->state_c);
-        hipFree(S->state_f);
+        (void)hipFree(S->state_c);
+        (void)hipFree(S->state_f);
       }
       SFQED_HIP(hipMalloc(&S->state_c, sizeof(uint64_t) * tiles));
       SFQED_HIP(hipMalloc(&S->state_f, sizeof(uint64_t) * tiles));
@@ -544,7 +564,7 @@ qed_status qed_build_rate_tables(const qed_table_cfg* cfg, void* stream, qed_tab
   }
   qed_tables* t = new qed_tables();
   std::memset(t, 0, sizeof(*t));
-  hipGetDevice(&t->device);
+  (void)hipGetDevice(&t->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   qed_status rc = build_tables(c, st, t);
   if (rc == QED_OK && hipStreamSynchronize(st) != hipSuccess) {
@@ -552,7 +572,7 @@ qed_status qed_build_rate_tables(const qed_table_cfg* cfg, void* stream, qed_tab
     rc = QED_ERR_HIP;
   }
   if (rc != QED_OK) {
-    if (t->mem) hipFree(t->mem);
+    if (t->mem) (void)hipFree(t->mem);
     delete t;
     return rc;
   }
@@ -562,7 +582,7 @@ qed_status qed_build_rate_tables(const qed_table_cfg* cfg, void* stream, qed_tab
 
 void qed_tables_free(qed_tables* t) {
   if (!t) return;
-  if (t->mem) hipFree(t->mem);
+  if (t->mem) (void)hipFree(t->mem);
   delete t;
 }
 

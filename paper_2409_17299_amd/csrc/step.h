@@ -10,10 +10,13 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kMergeThreads = 256;
+constexpr int kMergeItems = 8;
+constexpr int kMergeTile = kMergeThreads * kMergeItems;
 
 // device statistics words
 constexpr int kStatMaxEvents = 0;
 constexpr int kStatCapped = 1;
+constexpr int kStatEventParticles = 2;  // + 0 leptons, + 1 photons
 
 template <typename T>
 struct StepArgs {
@@ -51,6 +54,7 @@ struct ScanArgs {
   uint32_t epoch;
   unsigned long long* ticket;  // zero at launch
   int64_t num_tiles;
+  unsigned long long* event_particles;  // += number of particles with events
 };
 
 template <typename T>
@@ -85,8 +89,5 @@ template <typename T>
 hipError_t launch_sample(const TableView& tab, int process, const T* chi, const uint32_t* k, T* out, int64_t n,
                          hipStream_t st);
 
-// occupancy helpers (api.cpp)
-template <typename T, bool kPhoton>
-const void* count_kernel_ptr();
 
 }  // namespace sfqed

@@ -40,36 +40,52 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
 
 // ------------------------------------------------------------------ look-back
 // State word: [epoch:24][flag:2][value:38]; flag 1 = aggregate, 2 = inclusive prefix.
+// Flag and value travel in one 64-bit word, so relaxed device-scope atomics
+// suffice: no other data is published through it.  (Release/acquire at device
+// scope would write back / invalidate the XCD-local L2 at every probe.)
 constexpr uint64_t kValMask = (1ull << 38) - 1;
 
 __device__ __forceinline__ void lb_publish(uint64_t* st, uint32_t epoch, uint64_t flag, uint64_t val) {
   const uint64_t v = ((uint64_t)epoch << 40) | (flag << 38) | (val > kValMask ? kValMask : val);
-  __hip_atomic_store(st, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(st, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Run by one thread per tile.  Returns the exclusive prefix of the tile
-// (tile 0's prefix is `base`).
+// Run by all 64 lanes of one wave per tile.  Each probe reads the states of
+// the 64 preceding tiles at once: the aggregates up to the nearest inclusive
+// prefix are summed with a wave reduction, otherwise the window moves back by
+// 64 tiles.  Returns the exclusive prefix of the tile (tile 0's is `base`).
 __device__ int64_t lookback(uint64_t* st, int64_t tile, int64_t agg, int64_t base, uint32_t epoch) {
+  const int lane = lane_id();
   if (tile == 0) {
-    lb_publish(st, epoch, 2, (uint64_t)(base + agg));
+    if (lane == 0) lb_publish(st, epoch, 2, (uint64_t)(base + agg));
     return base;
   }
-  lb_publish(st + tile, epoch, 1, (uint64_t)agg);
+  if (lane == 0) lb_publish(st + tile, epoch, 1, (uint64_t)agg);
   int64_t excl = 0;
-  int64_t k = tile - 1;
+  int64_t top = tile - 1;  // lane l probes tile top - l
   while (true) {
-    const uint64_t v = __hip_atomic_load(st + k, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t ep = (uint32_t)(v >> 40);
-    const uint32_t fl = (uint32_t)((v >> 38) & 3);
-    if (ep != epoch || fl == 0) {
-      __builtin_amdgcn_s_sleep(1);
+    const int64_t k = top - lane;
+    uint64_t v = 0;
+    bool ready = true;
+    uint32_t fl = 2;  // tiles before the first one count as an empty prefix
+    if (k >= 0) {
+      v = __hip_atomic_load(st + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      fl = (uint32_t)((v >> 38) & 3);
+      ready = (uint32_t)(v >> 40) == epoch && fl != 0;
+    }
+    if (!__all(ready)) {
+      __builtin_amdgcn_s_sleep(2);
       continue;
     }
-    excl += (int64_t)(v & kValMask);
-    if (fl == 2) break;
-    --k;
+    const uint64_t pm = __ballot(fl == 2);
+    const int stop = pm ? __builtin_ctzll(pm) : 63;
+    int64_t val = (lane <= stop && k >= 0) ? (int64_t)(v & kValMask) : 0;
+    for (int off = 32; off > 0; off >>= 1) val += __shfl_xor(val, off);
+    excl += val;
+    if (pm) break;
+    top -= 64;
   }
-  lb_publish(st + tile, epoch, 2, (uint64_t)(excl + agg));
+  if (lane == 0) lb_publish(st + tile, epoch, 2, (uint64_t)(excl + agg));
   return excl;
 }
 
@@ -322,55 +338,127 @@ __device__ __forceinline__ LdsTables stage_tables(const StepArgs<T>& a, float* l
   return lt;
 }
 
-// ------------------------------------------------------------------ count kernel
-template <typename T, bool kPhoton>
-__global__ void __launch_bounds__(kStepThreads) k_count(StepArgs<T> a) {
+// ------------------------------------------------------------------ work distribution
+// Lepton kernels: lanes whose particle has finished take the next one from a
+// queue held by their wave; the wave refills that queue from the launch-wide
+// counter in chunks that shrink as the work runs out (large chunks keep the
+// atomics on the counter rare, small ones at the end balance the tail).
+struct WaveQueue {
+  uint64_t next, end;  // wave-uniform
+  bool done;
+};
+
+__device__ __forceinline__ void wq_init(WaveQueue& q) {
+  q.next = q.end = 0;
+  q.done = false;
+}
+
+// Returns the item index of this lane (>= n: none) for lanes with need set.
+__device__ __forceinline__ uint64_t wq_take(WaveQueue& q, bool need, uint64_t n, unsigned long long* ctr,
+                                            uint32_t waves) {
+  uint64_t m = __ballot(need);
+  uint64_t got = ~0ull;
+  while (m && !q.done) {
+    const uint64_t avail = q.end - q.next;
+    if (avail == 0) {
+      // guided chunk: about remaining / (4 waves), at least 64, at most 4096
+      uint64_t base = 0;
+      uint64_t chunk = 64;
+      if (lane_id() == 0) {
+        const uint64_t seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t rem = seen < n ? n - seen : 0;
+        chunk = rem / (4ull * waves);
+        chunk = chunk < 64 ? 64 : (chunk > 4096 ? 4096 : chunk);
+        base = atomicAdd(ctr, (unsigned long long)chunk);
+      }
+      base = readlane64(base, 0);
+      chunk = readlane64(chunk, 0);
+      if (base >= n) {
+        q.done = true;
+        break;
+      }
+      q.next = base;
+      q.end = base + chunk < n ? base + chunk : n;
+      continue;
+    }
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    const uint32_t take = (uint64_t)cnt < avail ? cnt : (uint32_t)avail;
+    const uint32_t r = mbcnt(m);
+    if (((m >> lane_id()) & 1ull) && r < take) got = q.next + r;
+    // lanes served drop out of the mask
+    uint64_t served = 0;
+    {
+      const uint64_t mine = (((m >> lane_id()) & 1ull) && r < take) ? 1ull : 0ull;
+      served = __ballot(mine != 0);
+    }
+    m &= ~served;
+    q.next += take;
+  }
+  return got;
+}
+
+// ------------------------------------------------------------------ count kernels
+// Leptons: event counts vary from 0 to hundreds, so lanes refill.
+template <typename T>
+__global__ void __launch_bounds__(kStepThreads) k_count_lepton(StepArgs<T> a) {
   extern __shared__ float lds[];
-  const LdsTables lt = stage_tables<T, kPhoton>(a, lds);
-  const int64_t n = a.n;
+  const LdsTables lt = stage_tables<T, false>(a, lds);
+  const uint64_t n = (uint64_t)a.n;
   const T q = a.species == 0 ? T(-1) : T(1);
+  const uint32_t waves = gridDim.x * (kStepThreads / 64);
+  WaveQueue wq;
+  wq_init(wq);
   Lane<T> L;
-  bool have = false, more = true;
+  bool have = false;
   int32_t local_max = 0;
   bool capped = false;
   while (true) {
-    const bool need = !have && more;
-    const uint64_t m = __ballot(need);
-    if (m) {
-      const int leader = __builtin_ctzll(m);
-      uint64_t base = 0;
-      if (lane_id() == leader) base = atomicAdd(&a.queue[0], (unsigned long long)__popcll(m));
-      base = readlane64(base, leader);
-      if (base + (uint64_t)__popcll(m) >= (uint64_t)n) more = false;
-      if (need) {
-        const uint64_t k = base + mbcnt(m);
-        if (k < (uint64_t)n) {
-          load_lane<T>(a, (int64_t)k, L);
-          have = true;
-        }
-      }
+    const uint64_t k = wq_take(wq, !have, n, &a.queue[0], waves);
+    if (!have && k < n) {
+      load_lane<T>(a, (int64_t)k, L);
+      have = true;
     }
     if (!__any(have)) break;
-    if (have) {
-      const bool fin = kPhoton ? photon_iter<T, false>(a, lt, L, 0) : lepton_iter<T, false>(a, lt, L, q, 0);
-      if (fin) {
-        const int64_t i = a.begin + L.k;
-        a.counts[L.k] = L.j;
-        if (a.src.nev) a.src.nev[i] = L.j;
-        if (L.j == 0) store_final<T>(a, L, !kPhoton && a.push);
-        local_max = L.j > local_max ? L.j : local_max;
-        capped |= L.capped;
-        have = false;
-      }
+    if (have && lepton_iter<T, false>(a, lt, L, q, 0)) {
+      const int64_t i = a.begin + L.k;
+      a.counts[L.k] = L.j;
+      if (a.src.nev) a.src.nev[i] = L.j;
+      if (L.j == 0) store_final<T>(a, L, a.push != 0);
+      local_max = L.j > local_max ? L.j : local_max;
+      capped |= L.capped;
+      have = false;
     }
   }
-  // wave max of the event counts
   for (int off = 32; off > 0; off >>= 1) {
     const int32_t o = __shfl_xor(local_max, off);
     local_max = o > local_max ? o : local_max;
   }
   if (lane_id() == 0 && local_max > 0) atomicMax(&a.stats[kStatMaxEvents], (unsigned long long)local_max);
   if (__any(capped) && lane_id() == 0) atomicOr(&a.stats[kStatCapped], 1ull);
+}
+
+// Photons: at most one event each; one photon per thread.
+template <typename T>
+__global__ void __launch_bounds__(kStepThreads) k_count_photon(StepArgs<T> a) {
+  extern __shared__ float lds[];
+  const LdsTables lt = stage_tables<T, true>(a, lds);
+  int32_t any_event = 0;
+  for (int64_t k = (int64_t)blockIdx.x * kStepThreads + threadIdx.x; k < a.n;
+       k += (int64_t)gridDim.x * kStepThreads) {
+    Lane<T> L;
+    load_lane<T>(a, k, L);
+    const int64_t i = a.begin + k;
+    if (a.src.alive[i] == 0) {  // a photon removed earlier is not processed
+      a.counts[k] = 0;
+      continue;
+    }
+    photon_iter<T, false>(a, lt, L, 0);
+    a.counts[k] = L.j;
+    if (a.src.nev) a.src.nev[i] = L.j;
+    if (L.j == 0) store_final<T>(a, L, false);
+    any_event |= L.j;
+  }
+  if (__any(any_event) && lane_id() == 0) atomicMax(&a.stats[kStatMaxEvents], 1ull);
 }
 
 // ------------------------------------------------------------------ scan kernel
@@ -411,6 +499,28 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
     sf[wave] = inf;
   }
   __syncthreads();
+  if (tid < 64) {
+    int64_t acc_c = 0;
+    int32_t acc_f = 0;
+    for (int wv = 0; wv < kScanThreads / 64; ++wv) {
+      acc_c += sc[wv];
+      acc_f += sf[wv];
+    }
+    const int64_t base = (tile == 0 && tid == 0) ? *s.cursor : 0;
+    const int64_t b0 = __shfl(base, 0);
+    const int64_t bc = lookback(s.state_c, tile, acc_c, b0, s.epoch);
+    const int64_t bf = lookback(s.state_f, tile, acc_f, 0, s.epoch);
+    if (tid == 0) {
+      s_base_c = bc;
+      s_base_f = bf;
+      if (tile == s.num_tiles - 1) {
+        *s.cursor = bc + acc_c;
+        *s.list_len = bf + acc_f;
+        atomicAdd(s.event_particles, (unsigned long long)(bf + acc_f));
+      }
+    }
+  }
+  __syncthreads();
   if (tid == 0) {
     int64_t acc_c = 0;
     int32_t acc_f = 0;
@@ -421,13 +531,6 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
       sf[wv] = acc_f;
       acc_c += tc;
       acc_f += tf;
-    }
-    const int64_t base = tile == 0 ? *s.cursor : 0;
-    s_base_c = lookback(s.state_c, tile, acc_c, base, s.epoch);
-    s_base_f = lookback(s.state_f, tile, acc_f, 0, s.epoch);
-    if (tile == s.num_tiles - 1) {
-      *s.cursor = s_base_c + acc_c;
-      *s.list_len = s_base_f + acc_f;
     }
   }
   __syncthreads();
@@ -444,53 +547,52 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
   }
 }
 
-// ------------------------------------------------------------------ write kernel
-template <typename T, bool kPhoton>
-__global__ void __launch_bounds__(kStepThreads) k_write(StepArgs<T> a) {
+// ------------------------------------------------------------------ write kernels
+template <typename T>
+__global__ void __launch_bounds__(kStepThreads) k_write_lepton(StepArgs<T> a) {
   extern __shared__ float lds[];
-  const LdsTables lt = stage_tables<T, kPhoton>(a, lds);
-  const int64_t n = *a.list_len;
+  const LdsTables lt = stage_tables<T, false>(a, lds);
+  const uint64_t n = (uint64_t)*a.list_len;
   const T q = a.species == 0 ? T(-1) : T(1);
+  const uint32_t waves = gridDim.x * (kStepThreads / 64);
+  WaveQueue wq;
+  wq_init(wq);
   Lane<T> L;
   int64_t obase = 0;
-  bool have = false, more = n > 0;
+  bool have = false;
   while (true) {
-    const bool need = !have && more;
-    const uint64_t m = __ballot(need);
-    if (m) {
-      const int leader = __builtin_ctzll(m);
-      uint64_t base = 0;
-      if (lane_id() == leader) base = atomicAdd(&a.queue[1], (unsigned long long)__popcll(m));
-      base = readlane64(base, leader);
-      if (base + (uint64_t)__popcll(m) >= (uint64_t)n) more = false;
-      if (need) {
-        const uint64_t e = base + mbcnt(m);
-        if (e < (uint64_t)n) {
-          const int64_t k = a.list[e];
-          load_lane<T>(a, k, L);
-          obase = a.offsets[k];
-          have = true;
-        }
-      }
+    const uint64_t e = wq_take(wq, !have, n, &a.queue[1], waves);
+    if (!have && e < n) {
+      const int64_t k = a.list[e];
+      load_lane<T>(a, k, L);
+      obase = a.offsets[k];
+      have = true;
     }
     if (!__any(have)) break;
-    if (have) {
-      const bool fin = kPhoton ? photon_iter<T, true>(a, lt, L, obase) : lepton_iter<T, true>(a, lt, L, q, obase);
-      if (fin) {
-        if (kPhoton) {
-          const int64_t i = a.begin + L.k;
-          if (a.positions) {
-            a.src.x[i] = L.x[0];
-            a.src.y[i] = L.x[1];
-            a.src.z[i] = L.x[2];
-          }
-          a.src.alive[i] = 0;
-        } else {
-          store_final<T>(a, L, true);
-        }
-        have = false;
-      }
+    if (have && lepton_iter<T, true>(a, lt, L, q, obase)) {
+      store_final<T>(a, L, true);
+      have = false;
     }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kStepThreads) k_write_photon(StepArgs<T> a) {
+  extern __shared__ float lds[];
+  const LdsTables lt = stage_tables<T, true>(a, lds);
+  const int64_t n = *a.list_len;
+  for (int64_t e = (int64_t)blockIdx.x * kStepThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kStepThreads) {
+    const int64_t k = a.list[e];
+    Lane<T> L;
+    load_lane<T>(a, k, L);
+    photon_iter<T, true>(a, lt, L, a.offsets[k]);
+    const int64_t i = a.begin + k;
+    if (a.positions) {
+      a.src.x[i] = L.x[0];
+      a.src.y[i] = L.x[1];
+      a.src.z[i] = L.x[2];
+    }
+    a.src.alive[i] = 0;
   }
 }
 
@@ -556,10 +658,10 @@ __global__ void k_sample(TableView tab, int process, const T* chi, const uint32_
 
 // ------------------------------------------------------------------ merge
 // Stable compaction of photons (alive != 0) over the virtual sequence
-// main[0, n_main) ++ app[0, n_app) into main.  Each tile loads all its fields
-// before publishing its aggregate, so writes of later tiles never overwrite
-// elements that are still to be read (the destination index of an element is
-// never above its source index within main).
+// main[0, n_main) ++ app[0, n_app) into main, kMergeItems per thread.  Each
+// tile holds all its surviving fields in registers before it publishes its
+// aggregate, so writes of later tiles (destination <= source within main)
+// never overwrite an element that is still to be read.
 template <typename T>
 __global__ void __launch_bounds__(kMergeThreads) k_merge_photons(MergeArgs<T> a) {
   __shared__ int32_t wsum[kMergeThreads / 64];
@@ -568,62 +670,93 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_photons(MergeArgs<T> a)
   if (tid == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1ull);
   __syncthreads();
   const int64_t tile = s_tile;
-  const int64_t g = tile * kMergeThreads + tid;
   const int64_t ntot = a.n_main + a.n_app;
-  bool ok = false;
-  T p[3] = {T(0), T(0), T(0)}, x[3] = {T(0), T(0), T(0)};
-  float w = 0.f;
-  double tau = 0.0;
-  uint64_t id = 0;
-  if (g < ntot) {
-    const bool in_main = g < a.n_main;
-    const SpeciesView<T>& s = in_main ? a.main : a.app;
-    const int64_t i = in_main ? g : g - a.n_main;
-    ok = s.alive[i] != 0;
-    if (ok) {
-      p[0] = s.px[i];
-      p[1] = s.py[i];
-      p[2] = s.pz[i];
-      if (a.positions) {
-        x[0] = s.x[i];
-        x[1] = s.y[i];
-        x[2] = s.z[i];
+  T p[kMergeItems][3], x[kMergeItems][3];
+  float w[kMergeItems];
+  double tau[kMergeItems];
+  uint64_t id[kMergeItems];
+  uint32_t okmask = 0;
+  // item i of this thread: tile * kMergeTile + i * kMergeThreads + tid (coalesced per item)
+#pragma unroll
+  for (int it = 0; it < kMergeItems; ++it) {
+    const int64_t g = tile * kMergeTile + (int64_t)it * kMergeThreads + tid;
+    bool ok = false;
+    if (g < ntot) {
+      const bool in_main = g < a.n_main;
+      const SpeciesView<T>& s = in_main ? a.main : a.app;
+      const int64_t i = in_main ? g : g - a.n_main;
+      ok = s.alive[i] != 0;
+      if (ok) {
+        p[it][0] = s.px[i];
+        p[it][1] = s.py[i];
+        p[it][2] = s.pz[i];
+        if (a.positions) {
+          x[it][0] = s.x[i];
+          x[it][1] = s.y[i];
+          x[it][2] = s.z[i];
+        }
+        w[it] = s.w[i];
+        tau[it] = s.tau[i];
+        id[it] = s.id[i];
       }
-      w = s.w[i];
-      tau = s.tau[i];
-      id = s.id[i];
+    }
+    okmask |= (ok ? 1u : 0u) << it;
+  }
+  // The tile's loads must have returned before its aggregate becomes visible
+  // (later tiles write into this tile's source range).  Consuming every loaded
+  // register in an empty asm makes the compiler wait for the loads here; the
+  // block barrier below then orders all waves before the publish.
+#pragma unroll
+  for (int it = 0; it < kMergeItems; ++it) {
+    if ((okmask >> it) & 1u) {
+      asm volatile("" ::"v"(p[it][0]), "v"(p[it][1]), "v"(p[it][2]), "v"(w[it]), "v"(tau[it]), "v"(id[it])
+                   : "memory");
+      if (a.positions) asm volatile("" ::"v"(x[it][0]), "v"(x[it][1]), "v"(x[it][2]) : "memory");
     }
   }
-  const uint64_t m = __ballot(ok);
+  // order within the tile: item-major, then thread (matches g)
+  int32_t pre[kMergeItems];
   const int lane = lane_id(), wave = tid >> 6;
-  if (lane == 0) wsum[wave] = __popcll(m);
-  __syncthreads();
-  if (tid == 0) {
-    int32_t acc = 0;
+  int32_t tile_total = 0;
+  for (int it = 0; it < kMergeItems; ++it) {
+    const uint64_t m = __ballot((okmask >> it) & 1u);
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int32_t before = 0, all = 0;
     for (int wv = 0; wv < kMergeThreads / 64; ++wv) {
-      const int32_t t = wsum[wv];
-      wsum[wv] = acc;
-      acc += t;
+      before += wv < wave ? wsum[wv] : 0;
+      all += wsum[wv];
     }
-    s_base = lookback(a.state, tile, acc, 0, a.epoch);
-    if (tile == a.num_tiles - 1) *a.out_count = s_base + acc;
+    pre[it] = tile_total + before + (int32_t)mbcnt(m);
+    tile_total += all;
+    __syncthreads();
+  }
+  if (tid < 64) {
+    const int64_t b = lookback(a.state, tile, tile_total, 0, a.epoch);
+    if (tid == 0) {
+      s_base = b;
+      if (tile == a.num_tiles - 1) *a.out_count = b + tile_total;
+    }
   }
   __syncthreads();
-  if (ok) {
-    const int64_t o = s_base + wsum[wave] + mbcnt(m);
-    const SpeciesView<T>& d = a.main;
-    d.px[o] = p[0];
-    d.py[o] = p[1];
-    d.pz[o] = p[2];
-    if (a.positions) {
-      d.x[o] = x[0];
-      d.y[o] = x[1];
-      d.z[o] = x[2];
+  const SpeciesView<T>& d = a.main;
+#pragma unroll
+  for (int it = 0; it < kMergeItems; ++it) {
+    if ((okmask >> it) & 1u) {
+      const int64_t o = s_base + pre[it];
+      d.px[o] = p[it][0];
+      d.py[o] = p[it][1];
+      d.pz[o] = p[it][2];
+      if (a.positions) {
+        d.x[o] = x[it][0];
+        d.y[o] = x[it][1];
+        d.z[o] = x[it][2];
+      }
+      d.w[o] = w[it];
+      d.tau[o] = tau[it];
+      d.id[o] = id[it];
+      d.alive[o] = 1;
     }
-    d.w[o] = w;
-    d.tau[o] = tau;
-    d.id[o] = id;
-    d.alive[o] = 1;
   }
 }
 
@@ -636,25 +769,25 @@ __global__ void k_count_alive(const uint8_t* a, int64_t n, unsigned long long* o
 }
 
 // ------------------------------------------------------------------ explicit instantiations via launchers
-template <typename T, bool kPhoton>
-hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
+template <typename K, typename A>
+hipError_t launch_step_kernel(K kernel, const A& a, int grid, size_t lds, hipStream_t st) {
   if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_count<T, kPhoton>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_count<T, kPhoton>), dim3(grid), dim3(kStepThreads), lds, st, a);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kStepThreads), lds, st, a);
   return hipGetLastError();
 }
 template <typename T, bool kPhoton>
+hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
+  if (kPhoton) return launch_step_kernel(&k_count_photon<T>, a, grid, lds, st);
+  return launch_step_kernel(&k_count_lepton<T>, a, grid, lds, st);
+}
+template <typename T, bool kPhoton>
 hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_write<T, kPhoton>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL((k_write<T, kPhoton>), dim3(grid), dim3(kStepThreads), lds, st, a);
-  return hipGetLastError();
+  if (kPhoton) return launch_step_kernel(&k_write_photon<T>, a, grid, lds, st);
+  return launch_step_kernel(&k_write_lepton<T>, a, grid, lds, st);
 }
 hipError_t launch_scan(const ScanArgs& s, hipStream_t st) {
   hipLaunchKernelGGL(k_scan, dim3((unsigned)s.num_tiles), dim3(kScanThreads), 0, st, s);

@@ -173,14 +173,16 @@ def crossed_field(n: int = 10_000_000, seed: int = 0, indices=None, fractions=(0
         nvec = np.cross(Ed, Bd)
         pm = np.sqrt(en * en - 1.0) if s < 2 else en
         d = np.zeros((idx.size, 3))
-        ok = np.zeros(idx.size, dtype=bool)
-        for attempt in range(16):
-            cand = direction(uniform(seed, 20 + 2 * attempt, gidx), uniform(seed, 21 + 2 * attempt, gidx))
-            good = (en - pm * np.einsum("ij,ij->i", nvec, cand)) / en >= 1e-2
-            take = good & ~ok
-            d[take] = cand[take]
-            ok |= good
-        assert ok.all()
+        todo = np.arange(idx.size)
+        for attempt in range(16):  # redraw directions with (energy - n.p)/energy < 1e-2
+            g = gidx[todo]
+            cand = direction(uniform(seed, 20 + 2 * attempt, g), uniform(seed, 21 + 2 * attempt, g))
+            good = (en[todo] - pm[todo] * np.einsum("ij,ij->i", nvec[todo], cand)) / en[todo] >= 1e-2
+            d[todo[good]] = cand[good]
+            todo = todo[~good]
+            if todo.size == 0:
+                break
+        assert todo.size == 0
         p = d * pm[:, None]
         chi_t = log_uniform(uniform(seed, 14, gidx), *chi_range)
         Em = chi_t / (en - np.einsum("ij,ij->i", nvec, p))
