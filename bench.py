@@ -47,12 +47,14 @@ def kernel_bytes(name: str, st: dict, n_main: list, n_step: int) -> float:
     if name == "scan":
         return P[1] * (4 + 8) + (ev_l + ev_p) * 4
     if name == "write_lepton":
-        return ev_l * (52 + 4 + 8 + 4 + 12 + 8) + n_emit * 41
+        # per particle with events: state 52 + w 4 (+ root/t_birth) + offset 8 + list 4, final p 12 + tau 8;
+        # per child: one 48-byte record
+        return ev_l * (52 + 4 + 8 + 4 + 12 + 8) + n_emit * 48
     if name == "count_photon":
         n = P[3]
         return n * (52 + 4) + (n - main_p) * 8 + (n - ev_p) * 8
     if name == "write_photon":
-        return ev_p * (52 + 4 + 8 + 4 + 1) + 2 * n_pair * 40
+        return ev_p * (52 + 4 + 8 + 4 + 1) + 2 * n_pair * 48
     raise KeyError(name)
 
 
@@ -70,7 +72,7 @@ class DeviceWorkload:
             self.pristine.append(pr)
             self.fields.append(sf.Fields.from_array(sp.fields if sp.fields.shape[0] else np_.zeros((1, 6)), dtype))
             self.main.append(sf.Store.empty(max(sp.n + caps[s], 1), dtype, photon=s == 2, nev=False))
-            self.app.append(sf.Store.empty(max(caps[s], 1), dtype, photon=s == 2, append=True, nev=False))
+            self.app.append(sf.AppendBuffer(max(caps[s], 1), dtype))
 
     def restore(self):
         for s in range(3):
@@ -140,6 +142,8 @@ def main(argv=None):
     ap.add_argument("--cpu-stride", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--gamma-min", type=float, default=2.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for the HBM counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU: the event generator runs on a single MI355X here "
@@ -154,13 +158,21 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}), flush=True)
+        return 0
     log(f"generating the crossed-field workload ({args.n} particles)")
     t0 = time.perf_counter()
     wl = synth.crossed_field(args.n)
     log(f"  generated in {time.perf_counter() - t0:.1f} s; dt = {wl.dt:.6g}")
     tables = sf.Tables()
     dtype = torch.float32
-    cfg = sf.step_cfg(push=False, gamma_min=args.gamma_min, profile=True)
+    cfg = sf.step_cfg(push=False, gamma_min=args.gamma_min, profile=True, nev=False)
 
     # size the append buffers with one generous step
     caps = [int(args.n * 12), int(args.n * 12), int(min(args.n * 100, (1 << 30) - 1024))]

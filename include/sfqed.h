@@ -96,14 +96,11 @@ void qed_tables_free(qed_tables *t);
 qed_status qed_tables_export(const qed_tables *t, int which, void *dst, size_t *bytes);
 
 /* ------------------------------------------------------------------ particles
- * One species, structure of arrays, caller-owned device pointers.  Momenta and
- * positions have the step's dtype.  x, y, z may all be NULL (positions not
- * advanced).  alive is required for photons (a photon that produced a pair is
- * marked 0) and ignored for leptons.  nev (optional) receives the number of
- * events of each processed particle in the last step.  root and t_birth are
- * used only in append buffers: root = species << 30 | index of the particle of
- * the input ensemble whose fields the particle sees; t_birth (dtype) is the
- * time within the step at which it was created. */
+ * The input ensemble: one species as a structure of arrays, caller-owned
+ * device pointers.  Momenta and positions have the step's dtype.  x, y, z may
+ * all be NULL (positions not advanced).  alive is required for photons (a
+ * photon that produced a pair is marked 0) and ignored for leptons.  nev
+ * (optional) receives each particle's number of events in the last step. */
 typedef struct {
   void *px, *py, *pz;
   void *x, *y, *z;
@@ -112,10 +109,44 @@ typedef struct {
   uint64_t *id;
   uint8_t *alive;
   int32_t *nev;
-  uint32_t *root;
-  void *t_birth;
   int64_t count, capacity;
 } qed_species;
+
+/* Appended particles: one 16-byte-aligned record per particle, written with
+ * full 16-byte stores (the children of one parent are contiguous records).
+ * root = species << 30 | index of the input particle whose fields the record
+ * sees; t_birth is the time within the step at which it was created; nev is
+ * its number of events (written when qed_step_cfg.nev is set); alive is 0 for
+ * a photon that produced a pair.  FP32 steps use qed_rec32 (48 bytes), FP64
+ * steps qed_rec64 (64 bytes). */
+typedef struct {
+  float px, py, pz, t_birth;
+  double tau;
+  uint64_t id;
+  float w;
+  uint32_t root;
+  int32_t nev;
+  uint32_t alive;
+} qed_rec32;
+
+typedef struct {
+  double px, py, pz, t_birth;
+  double tau;
+  uint64_t id;
+  float w;
+  uint32_t root;
+  int32_t nev;
+  uint32_t alive;
+} qed_rec64;
+
+/* One species of appended particles: `rec` holds capacity records; `pos`
+ * (NULL unless positions are advanced) holds x, y, z, unused per record in the
+ * step's dtype.  count is set by qed_step. */
+typedef struct {
+  void *rec;
+  void *pos;
+  int64_t count, capacity;
+} qed_append;
 
 /* Per-particle fields of one species (dtype of the step), indexed like the
  * particles when stride = 1, or one shared value when stride = 0. */
@@ -137,6 +168,7 @@ typedef struct {
   double gamma_min;             /* leptons with gamma < gamma_min do not emit (>= 1) */
   int64_t max_events;           /* per particle and step; reaching it is an error */
   int32_t profile;              /* 1: time every launch with HIP events into stats */
+  int32_t nev;                  /* 1: write event counts (nev) of appended particles */
 } qed_step_cfg;
 
 void qed_step_cfg_default(qed_step_cfg *cfg);
@@ -174,15 +206,16 @@ qed_status qed_init_tau(qed_ensemble *ens, uint64_t seed, uint32_t step, void *s
  * On QED_ERR_CAPACITY nothing is written past any capacity and
  * stats->required_capacity tells how much would have been needed; the
  * ensemble is then partly advanced and the caller restores it. */
-qed_status qed_step(const qed_tables *tab, const qed_step_cfg *cfg, qed_ensemble *ens, qed_species app[3],
+qed_status qed_step(const qed_tables *tab, const qed_step_cfg *cfg, qed_ensemble *ens, qed_append app[3],
                     double dt, uint64_t seed, uint32_t step, qed_step_stats *stats, void *stream);
 
 /* Merge (the merge of per-thread arrays of Sec. 4.2): drops photons with
  * alive = 0 from `ens` (stable), then appends the surviving particles of
- * `app` after each species.  Capacity of ens->s[k] must hold the result,
- * otherwise QED_ERR_CAPACITY and nothing is changed.  ens->s[k].count is
- * updated (blocking: one small device-to-host copy). */
-qed_status qed_merge(qed_ensemble *ens, const qed_species app[3], void *stream);
+ * `app` after each species, converting records to the ensemble's arrays.
+ * Capacity of ens->s[k] must hold the result, otherwise QED_ERR_CAPACITY and
+ * nothing is changed.  ens->s[k].count is updated (blocking: one small
+ * device-to-host copy). */
+qed_status qed_merge(qed_ensemble *ens, const qed_append app[3], void *stream);
 
 /* ------------------------------------------------------------------ kernels of the step, exposed for validation
  * Rates W (per unit time) of one process for given chi and energy (gamma for

@@ -42,8 +42,19 @@ class TableCfg(C.Structure):
 class CSpecies(C.Structure):
     _fields_ = [("px", C.c_void_p), ("py", C.c_void_p), ("pz", C.c_void_p), ("x", C.c_void_p),
                 ("y", C.c_void_p), ("z", C.c_void_p), ("w", C.c_void_p), ("tau", C.c_void_p),
-                ("id", C.c_void_p), ("alive", C.c_void_p), ("nev", C.c_void_p), ("root", C.c_void_p),
-                ("t_birth", C.c_void_p), ("count", C.c_int64), ("capacity", C.c_int64)]
+                ("id", C.c_void_p), ("alive", C.c_void_p), ("nev", C.c_void_p), ("count", C.c_int64),
+                ("capacity", C.c_int64)]
+
+
+class CAppend(C.Structure):
+    _fields_ = [("rec", C.c_void_p), ("pos", C.c_void_p), ("count", C.c_int64), ("capacity", C.c_int64)]
+
+
+def record_dtype(float_dtype) -> np.dtype:
+    """numpy layout of one appended record (qed_rec32 / qed_rec64)."""
+    f = np.dtype(float_dtype)
+    return np.dtype([("px", f), ("py", f), ("pz", f), ("t_birth", f), ("tau", np.float64), ("id", np.uint64),
+                     ("w", np.float32), ("root", np.uint32), ("nev", np.int32), ("alive", np.uint32)])
 
 
 class CFields(C.Structure):
@@ -58,7 +69,7 @@ class CEnsemble(C.Structure):
 class StepCfg(C.Structure):
     _fields_ = [("emission", C.c_int32), ("pair", C.c_int32), ("push", C.c_int32), ("sampler", C.c_int),
                 ("mlp", C.c_void_p), ("gamma_min", C.c_double), ("max_events", C.c_int64),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("nev", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -96,9 +107,9 @@ def lib():
             "qed_tables_geometry": (C.c_int, [v, C.POINTER(C.c_double), C.c_int]),
             "qed_step_cfg_default": (None, [C.POINTER(StepCfg)]),
             "qed_init_tau": (C.c_int, [C.POINTER(CEnsemble), C.c_uint64, C.c_uint32, v]),
-            "qed_step": (C.c_int, [v, C.POINTER(StepCfg), C.POINTER(CEnsemble), C.POINTER(CSpecies), C.c_double,
+            "qed_step": (C.c_int, [v, C.POINTER(StepCfg), C.POINTER(CEnsemble), C.POINTER(CAppend), C.c_double,
                                    C.c_uint64, C.c_uint32, C.POINTER(StepStats), v]),
-            "qed_merge": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CSpecies), v]),
+            "qed_merge": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CAppend), v]),
             "qed_eval_rate": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
             "qed_eval_particles": (C.c_int, [v, C.c_int, C.c_int, p, p, p, C.POINTER(CFields), i64, p, p, v]),
             "qed_sample": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
@@ -200,8 +211,6 @@ class Store:
     id: object
     alive: object = None
     nev: object = None
-    root: object = None
-    t_birth: object = None
     x: object = None
     y: object = None
     z: object = None
@@ -217,8 +226,8 @@ class Store:
         return self.px.dtype
 
     @classmethod
-    def empty(cls, capacity: int, dtype=None, photon: bool = False, append: bool = False, positions: bool = False,
-              nev: bool = True, device="cuda"):
+    def empty(cls, capacity: int, dtype=None, photon: bool = False, positions: bool = False, nev: bool = True,
+              device="cuda"):
         torch = _torch()
         dtype = dtype or torch.float32
         cap = max(int(capacity), 0)
@@ -228,9 +237,6 @@ class Store:
             s.alive = torch.ones(cap, dtype=torch.uint8, device=device)
         if nev:
             s.nev = z(torch.int32)
-        if append:
-            s.root = z(torch.int32)
-            s.t_birth = z(dtype)
         if positions:
             s.x, s.y, s.z = z(dtype), z(dtype), z(dtype)
         return s
@@ -258,7 +264,7 @@ class Store:
 
     def c(self) -> CSpecies:
         return CSpecies(*[_ptr(t) for t in (self.px, self.py, self.pz, self.x, self.y, self.z, self.w, self.tau,
-                                            self.id, self.alive, self.nev, self.root, self.t_birth)],
+                                            self.id, self.alive, self.nev)],
                         self.count, self.capacity)
 
     def host(self) -> dict:
@@ -267,13 +273,50 @@ class Store:
         out = {"p": np.stack([t[:n].double().cpu().numpy() for t in (self.px, self.py, self.pz)], axis=1),
                "w": self.w[:n].cpu().numpy(), "tau": self.tau[:n].cpu().numpy(),
                "id": self.id[:n].cpu().numpy().view(np.uint64)}
-        for name in ("alive", "nev", "root", "t_birth"):
+        for name in ("alive", "nev"):
             t = getattr(self, name)
             if t is not None:
-                a = t[:n].cpu().numpy()
-                out[name] = a.view(np.uint32) if name == "root" else (a.astype(np.float64) if name == "t_birth" else a)
+                out[name] = t[:n].cpu().numpy()
         if self.x is not None:
             out["x"] = np.stack([t[:n].double().cpu().numpy() for t in (self.x, self.y, self.z)], axis=1)
+        return out
+
+
+class AppendBuffer:
+    """Appended particles of one species: 16-byte-aligned records (qed_rec32 or
+    qed_rec64) in a torch uint8 tensor, plus optional positions (4 per record)."""
+
+    def __init__(self, capacity: int, dtype=None, positions: bool = False, device="cuda"):
+        torch = _torch()
+        self.dtype = dtype or torch.float32
+        self.np_float = np.float32 if self.dtype == torch.float32 else np.float64
+        self.rec_dtype = record_dtype(self.np_float)
+        cap = max(int(capacity), 0)
+        self.data = torch.zeros(max(cap, 1) * self.rec_dtype.itemsize, dtype=torch.uint8, device=device)
+        self.pos = torch.zeros(max(cap, 1) * 4, dtype=self.dtype, device=device) if positions else None
+        self.cap = cap
+        self.count = 0
+
+    @property
+    def capacity(self) -> int:
+        return self.cap
+
+    def c(self) -> CAppend:
+        return CAppend(_ptr(self.data), _ptr(self.pos), self.count, self.capacity)
+
+    def records(self, n: int | None = None) -> np.ndarray:
+        n = self.count if n is None else n
+        raw = self.data[: n * self.rec_dtype.itemsize].cpu().numpy()
+        return raw.view(self.rec_dtype)
+
+    def host(self) -> dict:
+        r = self.records()
+        out = {"p": np.stack([r["px"], r["py"], r["pz"]], axis=1).astype(np.float64), "w": r["w"].copy(),
+               "tau": r["tau"].copy(), "id": r["id"].copy(), "root": r["root"].copy(),
+               "t_birth": r["t_birth"].astype(np.float64), "nev": r["nev"].copy(),
+               "alive": r["alive"].astype(np.uint8)}
+        if self.pos is not None:
+            out["x"] = self.pos[: 4 * self.count].double().cpu().numpy().reshape(-1, 4)[:, :3]
         return out
 
 
@@ -318,11 +361,13 @@ def _ensemble(main: list, fields: list) -> CEnsemble:
     return e
 
 
-def step_cfg(emission=True, pair=True, push=True, gamma_min=1.0, max_events=1 << 20, profile=False) -> StepCfg:
+def step_cfg(emission=True, pair=True, push=True, gamma_min=1.0, max_events=1 << 20, profile=False,
+             nev=True) -> StepCfg:
     cfg = StepCfg()
     lib().qed_step_cfg_default(C.byref(cfg))
     cfg.emission, cfg.pair, cfg.push = int(emission), int(pair), int(push)
     cfg.gamma_min, cfg.max_events, cfg.profile = float(gamma_min), int(max_events), int(profile)
+    cfg.nev = int(nev)
     return cfg
 
 
@@ -336,10 +381,9 @@ def step(tables: Tables, main: list, fields: list, app: list, dt: float, seed: i
     """One global step (Algorithms 1 and 2).  Updates main/app in place and app counts."""
     cfg = cfg if cfg is not None else step_cfg()
     e = _ensemble(main, fields)
-    a = (CSpecies * 3)(*[s.c() for s in app])
     for s in app:
         s.count = 0
-    a = (CSpecies * 3)(*[s.c() for s in app])
+    a = (CAppend * 3)(*[s.c() for s in app])
     st = StepStats()
     rc = lib().qed_step(tables.handle, C.byref(cfg), C.byref(e), a, float(dt), C.c_uint64(seed),
                         C.c_uint32(step_index), C.byref(st), _stream(stream))
@@ -352,7 +396,7 @@ def step(tables: Tables, main: list, fields: list, app: list, dt: float, seed: i
 
 def merge(main: list, fields: list, app: list, stream=None):
     e = _ensemble(main, fields)
-    a = (CSpecies * 3)(*[s.c() for s in app])
+    a = (CAppend * 3)(*[s.c() for s in app])
     _check(lib().qed_merge(C.byref(e), a, _stream(stream)))
     for k in range(3):
         main[k].count = int(e.s[k].count)

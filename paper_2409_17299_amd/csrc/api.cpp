@@ -131,8 +131,6 @@ SpeciesView<T> view_of(const qed_species& s) {
   v.id = s.id;
   v.alive = s.alive;
   v.nev = s.nev;
-  v.root = s.root;
-  v.tb = static_cast<T*>(s.t_birth);
   return v;
 }
 
@@ -149,7 +147,7 @@ FieldView<T> fields_of(const qed_fields& f) {
   return v;
 }
 
-bool species_ok(const qed_species& s, bool photon, bool positions, bool is_append) {
+bool species_ok(const qed_species& s, bool photon, bool positions) {
   if (s.count < 0 || s.capacity < s.count) return false;
   if (s.capacity == 0) return true;
   if (!s.px || !s.py || !s.pz || !s.w || !s.tau || !s.id) return false;
@@ -157,8 +155,15 @@ bool species_ok(const qed_species& s, bool photon, bool positions, bool is_appen
   const int nx = (s.x != nullptr) + (s.y != nullptr) + (s.z != nullptr);
   if (nx != 0 && nx != 3) return false;
   if ((nx == 3) != positions) return false;
-  if (is_append && (!s.root || !s.t_birth)) return false;
   if (s.capacity >= (int64_t(1) << 30)) return false;  // root index field
+  return true;
+}
+
+bool append_ok(const qed_append& a, bool positions) {
+  if (a.capacity < 0) return false;
+  if (a.capacity == 0) return true;
+  if (!a.rec || (reinterpret_cast<uintptr_t>(a.rec) & 15u) != 0) return false;
+  if (positions && (!a.pos || (reinterpret_cast<uintptr_t>(a.pos) & 15u) != 0)) return false;
   return true;
 }
 
@@ -218,7 +223,7 @@ struct EventLog {
 // store.
 template <typename T>
 qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const qed_step_cfg* cfg,
-                      const qed_ensemble* ens, qed_species* app, int species, bool from_main, int64_t begin,
+                      const qed_ensemble* ens, qed_append* app, int species, bool from_main, int64_t begin,
                       int64_t n, double dt, uint64_t seed, uint32_t step, int* slot, bool positions, EventLog& log,
                       qed_step_stats* stats) {
   if (n <= 0) return QED_OK;
@@ -231,10 +236,11 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   const bool photon = species == 2;
   StepArgs<T> a;
   std::memset(&a, 0, sizeof(a));
-  a.src = from_main ? view_of<T>(ens->s[species]) : view_of<T>(app[species]);
   if (from_main) {
-    a.src.root = nullptr;
-    a.src.tb = nullptr;
+    a.src = view_of<T>(ens->s[species]);
+  } else {
+    a.src_rec = static_cast<Rec<T>*>(app[species].rec);
+    a.src_pos = static_cast<T*>(app[species].pos);
   }
   a.species = species;
   a.from_main = from_main ? 1 : 0;
@@ -243,12 +249,15 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   for (int k = 0; k < 3; ++k) a.f[k] = fields_of<T>(ens->f[k]);
   int64_t* cursor;
   if (photon) {
-    a.out[0] = view_of<T>(app[0]);
-    a.out[1] = view_of<T>(app[1]);
+    a.out_rec[0] = static_cast<Rec<T>*>(app[0].rec);
+    a.out_rec[1] = static_cast<Rec<T>*>(app[1].rec);
+    a.out_pos[0] = static_cast<T*>(app[0].pos);
+    a.out_pos[1] = static_cast<T*>(app[1].pos);
     a.out_cap = std::min(app[0].capacity, app[1].capacity);
     cursor = reinterpret_cast<int64_t*>(S->ctrl + kCurLepton);
   } else {
-    a.out[0] = view_of<T>(app[2]);
+    a.out_rec[0] = static_cast<Rec<T>*>(app[2].rec);
+    a.out_pos[0] = static_cast<T*>(app[2].pos);
     a.out_cap = app[2].capacity;
     cursor = reinterpret_cast<int64_t*>(S->ctrl + kCurPhoton);
   }
@@ -265,6 +274,7 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   a.pair = cfg->pair;
   a.push = cfg->push;
   a.positions = positions ? 1 : 0;
+  a.write_nev = cfg->nev ? 1 : 0;
   a.gamma_min = cfg->gamma_min;
   a.max_events = cfg->max_events;
   a.tab = tab->view;
@@ -323,7 +333,7 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
 }
 
 template <typename T>
-qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble* ens, qed_species* app,
+qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble* ens, qed_append* app,
                      double dt, uint64_t seed, uint32_t step, qed_step_stats* stats, hipStream_t st) {
   Scratch* S = scratch_for_current_device();
   if (!S) {
@@ -422,51 +432,35 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
 }
 
 template <typename T>
-qed_status merge_impl(qed_ensemble* ens, const qed_species* app, hipStream_t st) {
+qed_status merge_impl(qed_ensemble* ens, const qed_append* app, hipStream_t st) {
   Scratch* S = scratch_for_current_device();
   if (!S) return QED_ERR_HIP;
   std::lock_guard<std::mutex> lk(S->mu);
   const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
-  // leptons: append after the survivors (leptons do not die)
+  // leptons never die: their records are appended after the input ensemble
   for (int s = 0; s < 2; ++s)
     if (ens->s[s].count + app[s].count > ens->s[s].capacity) {
       set_error("merge: lepton capacity");
       return QED_ERR_CAPACITY;
     }
-  // photons: count survivors first
+  // photons: count the survivors first
   SFQED_HIP(hipMemsetAsync(S->ctrl + kAliveCount, 0, sizeof(uint64_t), st));
-  SFQED_HIP(launch_count_alive(ens->s[2].alive, ens->s[2].count, reinterpret_cast<unsigned long long*>(S->ctrl + kAliveCount), st));
-  SFQED_HIP(launch_count_alive(app[2].alive, app[2].count, reinterpret_cast<unsigned long long*>(S->ctrl + kAliveCount), st));
+  auto* cnt = reinterpret_cast<unsigned long long*>(S->ctrl + kAliveCount);
+  SFQED_HIP(launch_count_alive(ens->s[2].alive, ens->s[2].count, cnt, st));
+  SFQED_HIP(launch_count_alive_rec<T>(static_cast<const Rec<T>*>(app[2].rec), app[2].count, cnt, st));
   uint64_t alive_total = 0;
-  SFQED_HIP(hipMemcpyAsync(&alive_total, S->ctrl + kAliveCount, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  SFQED_HIP(hipMemcpyAsync(&alive_total, cnt, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   SFQED_HIP(hipStreamSynchronize(st));
   if ((int64_t)alive_total > ens->s[2].capacity) {
     set_error("merge: photon capacity");
     return QED_ERR_CAPACITY;
   }
-  for (int s = 0; s < 2; ++s) {
-    const qed_species& m = ens->s[s];
-    const qed_species& a = app[s];
-    const int64_t n = a.count, o = m.count;
-    if (n == 0) continue;
-    const size_t sT = sizeof(T);
-    SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.px) + o, a.px, sT * n, hipMemcpyDeviceToDevice, st));
-    SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.py) + o, a.py, sT * n, hipMemcpyDeviceToDevice, st));
-    SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.pz) + o, a.pz, sT * n, hipMemcpyDeviceToDevice, st));
-    if (positions) {
-      SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.x) + o, a.x, sT * n, hipMemcpyDeviceToDevice, st));
-      SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.y) + o, a.y, sT * n, hipMemcpyDeviceToDevice, st));
-      SFQED_HIP(hipMemcpyAsync(static_cast<T*>(m.z) + o, a.z, sT * n, hipMemcpyDeviceToDevice, st));
-    }
-    SFQED_HIP(hipMemcpyAsync(m.w + o, a.w, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
-    SFQED_HIP(hipMemcpyAsync(m.tau + o, a.tau, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    SFQED_HIP(hipMemcpyAsync(m.id + o, a.id, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, st));
-  }
+  for (int s = 0; s < 2; ++s)
+    SFQED_HIP(launch_append_records<T>(view_of<T>(ens->s[s]), ens->s[s].count, static_cast<const Rec<T>*>(app[s].rec),
+                                       static_cast<const T*>(app[s].pos), app[s].count, positions ? 1 : 0, st));
   const int64_t ntot = ens->s[2].count + app[2].count;
   int64_t new_photons = 0;
   if (ntot > 0) {
-    qed_status rc = ensure_scratch(S, 1);
-    if (rc != QED_OK) return rc;
     const int64_t tiles = (ntot + kMergeTile - 1) / kMergeTile;
     if (tiles > S->tiles_cap) {
       if (S->state_c) {
@@ -484,7 +478,8 @@ qed_status merge_impl(qed_ensemble* ens, const qed_species* app, hipStream_t st)
     SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t), st));
     MergeArgs<T> m;
     m.main = view_of<T>(ens->s[2]);
-    m.app = view_of<T>(app[2]);
+    m.app = static_cast<const Rec<T>*>(app[2].rec);
+    m.app_pos = static_cast<const T*>(app[2].pos);
     m.n_main = ens->s[2].count;
     m.n_app = app[2].count;
     m.positions = positions ? 1 : 0;
@@ -621,6 +616,7 @@ void qed_step_cfg_default(qed_step_cfg* c) {
   c->gamma_min = 1.0;
   c->max_events = 1 << 20;
   c->profile = 0;
+  c->nev = 1;
 }
 
 qed_status qed_init_tau(qed_ensemble* ens, uint64_t seed, uint32_t step, void* stream) {
@@ -635,7 +631,7 @@ qed_status qed_init_tau(qed_ensemble* ens, uint64_t seed, uint32_t step, void* s
   return QED_OK;
 }
 
-qed_status qed_step(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble* ens, qed_species app[3], double dt,
+qed_status qed_step(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble* ens, qed_append app[3], double dt,
                     uint64_t seed, uint32_t step, qed_step_stats* stats, void* stream) {
   if (!tab || !cfg || !ens || !app) {
     set_error("null argument");
@@ -648,7 +644,7 @@ qed_status qed_step(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble
   }
   const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
   for (int s = 0; s < 3; ++s) {
-    if (!species_ok(ens->s[s], s == 2, positions, false) || !species_ok(app[s], s == 2, positions, true) ||
+    if (!species_ok(ens->s[s], s == 2, positions) || !append_ok(app[s], positions) ||
         !fields_ok(ens->f[s], ens->s[s].count)) {
       set_error("invalid species " + std::to_string(s));
       return QED_ERR_ARG;
@@ -659,11 +655,12 @@ qed_status qed_step(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble
   return step_impl<double>(tab, cfg, ens, app, dt, seed, step, stats, st);
 }
 
-qed_status qed_merge(qed_ensemble* ens, const qed_species app[3], void* stream) {
+qed_status qed_merge(qed_ensemble* ens, const qed_append app[3], void* stream) {
   if (!ens || !app) return QED_ERR_ARG;
   const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
   for (int s = 0; s < 3; ++s) {
-    if (!species_ok(ens->s[s], s == 2, positions, false) || !species_ok(app[s], s == 2, positions, false))
+    if (!species_ok(ens->s[s], s == 2, positions) || !append_ok(app[s], positions) || app[s].count < 0 ||
+        app[s].count > app[s].capacity)
       return QED_ERR_ARG;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);

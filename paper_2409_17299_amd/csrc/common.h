@@ -65,13 +65,26 @@ __device__ __forceinline__ uint4 draw(uint64_t seed, uint64_t id, uint32_t step,
                 make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
 }
 
-// -ln(u) for u = (k + 1/2) 2^-32, in FP64 (optical depths are FP64)
+// -ln(u) for u = (k + 1/2) 2^-32 in FP64 (the FP64 path), and in FP32 for the
+// FP32 path (event-time arithmetic is FP32; the optical depth is still
+// accumulated in FP64).  For u > 1/2 the FP32 form uses 1 - u = (~k + 1/2) 2^-32,
+// which is exact, through log1p.
 __device__ __forceinline__ double exp_depth(uint32_t k) {
   return -log(((double)k + 0.5) * 0x1p-32);
 }
+__device__ __forceinline__ float exp_depth32(uint32_t k) {
+  if (k & 0x80000000u) return -log1pf(-((float)(~k) + 0.5f) * 0x1p-32f);
+  return -logf(((float)k + 0.5f) * 0x1p-32f);
+}
+template <typename T>
+__device__ __forceinline__ double exp_depth_t(uint32_t k) {
+  if constexpr (sizeof(T) == 4) return (double)exp_depth32(k);
+  else return exp_depth(k);
+}
 
 // ---------------------------------------------------------------------------
-// Views of one species and of its fields (T = float or double).
+// Views of one species (structure of arrays) and of its fields
+// (T = float or double).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SpeciesView {
@@ -82,14 +95,62 @@ struct SpeciesView {
   uint64_t* id;
   uint8_t* alive;  // nullable for leptons
   int32_t* nev;    // nullable
-  uint32_t* root;  // nullable: then root = species << 30 | index
-  T* tb;           // nullable: then 0
 };
 
 template <typename T>
 struct FieldView {
   const T *ex, *ey, *ez, *bx, *by, *bz;
   int64_t stride;
+};
+
+// Appended particle: one 16-byte-aligned record (the layout of qed_rec32 /
+// qed_rec64), moved with whole 16-byte loads and stores.
+template <typename T>
+struct alignas(16) Rec {
+  T px, py, pz, tb;
+  double tau;
+  uint64_t id;
+  float w;
+  uint32_t root;
+  int32_t nev;
+  uint32_t alive;
+};
+static_assert(sizeof(Rec<float>) == 48, "record layout");
+static_assert(sizeof(Rec<double>) == 64, "record layout");
+
+template <typename T>
+__device__ __forceinline__ void rec_load(const Rec<T>* base, int64_t i, Rec<T>& r) {
+  const uint4* s = reinterpret_cast<const uint4*>(base + i);
+  uint4* d = reinterpret_cast<uint4*>(&r);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(Rec<T>) / 16); ++k) d[k] = s[k];
+}
+
+template <typename T>
+__device__ __forceinline__ void rec_store(Rec<T>* base, int64_t i, const Rec<T>& r) {
+  uint4* d = reinterpret_cast<uint4*>(base + i);
+  const uint4* s = reinterpret_cast<const uint4*>(&r);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(Rec<T>) / 16); ++k) d[k] = s[k];
+}
+
+// Stores only the 16-byte chunks [k0, k1) of a record.
+template <typename T>
+__device__ __forceinline__ void rec_store_part(Rec<T>* base, int64_t i, const Rec<T>& r, int k0, int k1) {
+  uint4* d = reinterpret_cast<uint4*>(base + i);
+  const uint4* s = reinterpret_cast<const uint4*>(&r);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(Rec<T>) / 16); ++k)
+    if (k >= k0 && k < k1) d[k] = s[k];
+}
+
+// chunk indices: momenta (and t_birth) | tau, id | w, root, nev, alive
+template <typename T>
+struct RecChunks {
+  static constexpr int kMomEnd = sizeof(T) == 4 ? 1 : 2;
+  static constexpr int kTau = kMomEnd;
+  static constexpr int kTail = kMomEnd + 1;
+  static constexpr int kCount = kMomEnd + 2;
 };
 
 }  // namespace sfqed

@@ -20,23 +20,26 @@ constexpr int kStatEventParticles = 2;  // + 0 leptons, + 1 photons
 
 template <typename T>
 struct StepArgs {
-  SpeciesView<T> src;
-  int32_t species;    // species of src (0 e-, 1 e+, 2 photon)
-  int32_t from_main;  // 1: src is the input ensemble (root = species << 30 | index)
-  int64_t begin, n;   // particles [begin, begin + n) of src
+  SpeciesView<T> src;  // the input ensemble (from_main)
+  Rec<T>* src_rec;     // or appended records
+  T* src_pos;          // their positions (4 per record) or null
+  int32_t species;     // species of the source (0 e-, 1 e+, 2 photon)
+  int32_t from_main;   // 1: source is the input ensemble (root = species << 30 | index)
+  int64_t begin, n;    // particles [begin, begin + n) of the source
   FieldView<T> f[3];
-  SpeciesView<T> out[2];  // leptons: out[0] photons; photons: out[0] e-, out[1] e+
+  Rec<T>* out_rec[2];  // leptons: out[0] photons; photons: out[0] e-, out[1] e+
+  T* out_pos[2];
   int64_t out_cap;
-  int32_t* counts;    // [n]
-  int64_t* offsets;   // [n]
-  int32_t* list;      // [n]
+  int32_t* counts;     // [n]
+  int64_t* offsets;    // [n]
+  int32_t* list;       // [n]
   const int64_t* list_len;
   unsigned long long* queue;  // [2] work counters of the count and write kernels (zero at launch)
   unsigned long long* stats;
   double dt;
   uint64_t seed;
   uint32_t step;
-  int32_t emission, pair, push, positions;
+  int32_t emission, pair, push, positions, write_nev;
   double gamma_min;
   int64_t max_events;
   TableView tab;
@@ -59,7 +62,9 @@ struct ScanArgs {
 
 template <typename T>
 struct MergeArgs {
-  SpeciesView<T> main, app;
+  SpeciesView<T> main;
+  const Rec<T>* app;
+  const T* app_pos;
   int64_t n_main, n_app;
   int32_t positions;
   uint64_t* state;
@@ -77,6 +82,11 @@ hipError_t launch_scan(const ScanArgs& s, hipStream_t st);
 template <typename T>
 hipError_t launch_merge_photons(const MergeArgs<T>& a, hipStream_t st);
 hipError_t launch_count_alive(const uint8_t* alive, int64_t n, unsigned long long* out, hipStream_t st);
+template <typename T>
+hipError_t launch_count_alive_rec(const Rec<T>* rec, int64_t n, unsigned long long* out, hipStream_t st);
+template <typename T>
+hipError_t launch_append_records(const SpeciesView<T>& dst, int64_t at, const Rec<T>* rec, const T* pos, int64_t n,
+                                 int positions, hipStream_t st);
 template <typename T>
 hipError_t launch_init_tau(double* tau, const uint64_t* id, int64_t n, uint64_t seed, uint32_t step, hipStream_t st);
 template <typename T>

@@ -95,34 +95,58 @@ struct Lane {
   int64_t k;
   T p[3], x[3], E[3], B[3];
   double tau;
-  T t;
+  T t, t0;
   uint64_t id;
   uint32_t root;
   float w;
   int32_t j;
   bool capped;
+  bool changed;  // state differs from what was loaded
 };
 
 template <typename T>
 __device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<T>& L) {
   const int64_t i = a.begin + k;
-  const SpeciesView<T>& s = a.src;
   L.k = k;
-  L.p[0] = s.px[i];
-  L.p[1] = s.py[i];
-  L.p[2] = s.pz[i];
-  if (a.positions) {
-    L.x[0] = s.x[i];
-    L.x[1] = s.y[i];
-    L.x[2] = s.z[i];
+  if (a.from_main) {
+    const SpeciesView<T>& s = a.src;
+    L.p[0] = s.px[i];
+    L.p[1] = s.py[i];
+    L.p[2] = s.pz[i];
+    if (a.positions) {
+      L.x[0] = s.x[i];
+      L.x[1] = s.y[i];
+      L.x[2] = s.z[i];
+    } else {
+      L.x[0] = L.x[1] = L.x[2] = T(0);
+    }
+    L.tau = s.tau[i];
+    L.id = s.id[i];
+    L.w = s.w[i];
+    L.root = ((uint32_t)a.species << 30) | (uint32_t)i;
+    L.t = T(0);
+    L.t0 = T(0);
   } else {
-    L.x[0] = L.x[1] = L.x[2] = T(0);
+    Rec<T> r;
+    rec_load<T>(a.src_rec, i, r);
+    L.p[0] = r.px;
+    L.p[1] = r.py;
+    L.p[2] = r.pz;
+    L.t = r.tb;
+    L.t0 = r.tb;
+    L.tau = r.tau;
+    L.id = r.id;
+    L.w = r.w;
+    L.root = r.root;
+    if (a.positions) {
+      const T* q = a.src_pos + 4 * i;
+      L.x[0] = q[0];
+      L.x[1] = q[1];
+      L.x[2] = q[2];
+    } else {
+      L.x[0] = L.x[1] = L.x[2] = T(0);
+    }
   }
-  L.tau = s.tau[i];
-  L.id = s.id[i];
-  L.w = s.w[i];
-  L.root = a.from_main ? (((uint32_t)a.species << 30) | (uint32_t)i) : s.root[i];
-  L.t = s.tb ? s.tb[i] : T(0);
   const uint32_t sp = L.root >> 30;
   const int64_t idx = (int64_t)(L.root & 0x3FFFFFFFu);
   const FieldView<T>& f0 = a.f[0];
@@ -144,23 +168,50 @@ __device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<
   L.B[2] = bz[o];
   L.j = 0;
   L.capped = false;
+  L.changed = false;
 }
 
+// Final state of a processed particle: momentum (when it changed), position,
+// optical depth; for records also the event count and alive flag when asked.
 template <typename T>
-__device__ __forceinline__ void store_final(const StepArgs<T>& a, const Lane<T>& L, bool momentum) {
+__device__ __forceinline__ void store_final(const StepArgs<T>& a, const Lane<T>& L, bool momentum, bool died) {
   const int64_t i = a.begin + L.k;
-  const SpeciesView<T>& s = a.src;
-  if (momentum) {
-    s.px[i] = L.p[0];
-    s.py[i] = L.p[1];
-    s.pz[i] = L.p[2];
+  if (!L.changed && !died && !(a.write_nev && !a.from_main)) return;  // W = 0 all along: nothing moved
+  if (a.from_main) {
+    const SpeciesView<T>& s = a.src;
+    if (momentum) {
+      s.px[i] = L.p[0];
+      s.py[i] = L.p[1];
+      s.pz[i] = L.p[2];
+    }
+    if (a.positions) {
+      s.x[i] = L.x[0];
+      s.y[i] = L.x[1];
+      s.z[i] = L.x[2];
+    }
+    s.tau[i] = L.tau;
+    if (died) s.alive[i] = 0;
+    return;
   }
+  using C = RecChunks<T>;
+  Rec<T> r;
+  r.px = L.p[0];
+  r.py = L.p[1];
+  r.pz = L.p[2];
+  r.tb = L.t0;
+  r.tau = L.tau;
+  r.id = L.id;
+  r.w = L.w;
+  r.root = L.root;
+  r.nev = L.j;
+  r.alive = died ? 0u : 1u;
+  rec_store_part<T>(a.src_rec, i, r, momentum ? 0 : C::kTau, (a.write_nev || died) ? C::kCount : C::kTail);
   if (a.positions) {
-    s.x[i] = L.x[0];
-    s.y[i] = L.x[1];
-    s.z[i] = L.x[2];
+    T* q = a.src_pos + 4 * i;
+    q[0] = L.x[0];
+    q[1] = L.x[1];
+    q[2] = L.x[2];
   }
-  s.tau[i] = L.tau;
 }
 
 // Tables as the kernels see them: FP32 tables staged in LDS, FP64 in HBM.
@@ -204,23 +255,27 @@ __device__ __forceinline__ void advance_lepton(const StepArgs<T>& a, Lane<T>& L,
 }
 
 template <typename T>
-__device__ __forceinline__ void write_child(const SpeciesView<T>& o, int64_t idx, const T p[3], const T x[3],
+__device__ __forceinline__ void write_child(Rec<T>* out, T* pos, int64_t idx, const T p[3], const T x[3],
                                             bool positions, float w, double tau, uint64_t id, uint32_t root, T tb) {
-  o.px[idx] = p[0];
-  o.py[idx] = p[1];
-  o.pz[idx] = p[2];
+  Rec<T> r;
+  r.px = p[0];
+  r.py = p[1];
+  r.pz = p[2];
+  r.tb = tb;
+  r.tau = tau;
+  r.id = id;
+  r.w = w;
+  r.root = root;
+  r.nev = 0;
+  r.alive = 1u;
+  rec_store<T>(out, idx, r);
   if (positions) {
-    o.x[idx] = x[0];
-    o.y[idx] = x[1];
-    o.z[idx] = x[2];
+    T* q = pos + 4 * idx;
+    q[0] = x[0];
+    q[1] = x[1];
+    q[2] = x[2];
+    q[3] = T(0);
   }
-  o.w[idx] = w;
-  o.tau[idx] = tau;
-  o.id[idx] = id;
-  o.root[idx] = root;
-  o.tb[idx] = tb;
-  if (o.alive) o.alive[idx] = 1;
-  if (o.nev) o.nev[idx] = 0;
 }
 
 // One sub-cycle of Algorithm 1 for a lepton.  Returns true when the particle
@@ -232,13 +287,15 @@ __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTable
   if (!(L.t < dtT)) return true;
   const T g = sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
   T W = T(0);
-  if (a.emission && !L.capped && (double)g >= a.gamma_min) W = rate_of<T>(a, lt, 0, chi_of<T>(L.p, g, L.E, L.B), g);
+  const T chi0 = chi_of<T>(L.p, g, L.E, L.B);
+  if (a.emission && !L.capped && (double)g >= a.gamma_min) W = rate_of<T>(a, lt, 0, chi0, g);
   const T rem = dtT - L.t;
   const double X = (double)W * (double)rem;
   if (!(W > T(0)) || L.tau > X) {  // no event before the end of the step
     L.tau -= X;
     advance_lepton<T>(a, L, q, rem);
     L.t = dtT;
+    L.changed |= X > 0.0 || a.push || a.positions;
     return true;
   }
   T h = (T)L.tau / W;  // the optical depth runs out after h
@@ -246,8 +303,11 @@ __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTable
   advance_lepton<T>(a, L, q, h);
   L.t += h;
   const uint4 u = draw(a.seed, L.id, a.step, (uint32_t)L.j);
-  const T g2 = sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
-  const T chi_e = chi_of<T>(L.p, g2, L.E, L.B);  // the particle as it is at the event
+  T chi_e = chi0;  // the particle as it is at the event (unchanged unless pushed)
+  if (a.push) {
+    const T g2 = sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
+    chi_e = chi_of<T>(L.p, g2, L.E, L.B);
+  }
   T d, omd;
   sample_of<T>(a, lt, 0, chi_e, u.x, d, omd);
   if (kWrite) {
@@ -255,14 +315,15 @@ __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTable
     if (o < a.out_cap) {
       const uint4 v = draw(a.seed, L.id, a.step, (uint32_t)L.j | 0x80000000u);
       const T k[3] = {d * L.p[0], d * L.p[1], d * L.p[2]};
-      write_child<T>(a.out[0], o, k, L.x, a.positions, L.w, exp_depth(u.z),
+      write_child<T>(a.out_rec[0], a.out_pos[0], o, k, L.x, a.positions, L.w, exp_depth_t<T>(u.z),
                      (uint64_t)v.x | ((uint64_t)v.y << 32), L.root, L.t);
     }
   }
   L.p[0] *= omd;  // collinear recoil: photon k = delta p, lepton (1 - delta) p
   L.p[1] *= omd;
   L.p[2] *= omd;
-  L.tau = exp_depth(u.y);
+  L.tau = exp_depth_t<T>(u.y);
+  L.changed = true;
   ++L.j;
   if (L.j >= a.max_events) L.capped = true;
   return false;
@@ -289,6 +350,7 @@ __device__ __forceinline__ bool photon_iter(const StepArgs<T>& a, const LdsTable
       L.x[2] += L.p[2] * inv_eps * rem;
     }
     L.t = dtT;
+    L.changed |= X > 0.0 || a.positions;
     return true;
   }
   T h = (T)L.tau / W;
@@ -309,13 +371,14 @@ __device__ __forceinline__ bool photon_iter(const StepArgs<T>& a, const LdsTable
       const uint4 v = draw(a.seed, L.id, a.step, 0x80000000u);
       const T pe[3] = {xi * L.p[0], xi * L.p[1], xi * L.p[2]};
       const T pp[3] = {omx * L.p[0], omx * L.p[1], omx * L.p[2]};
-      write_child<T>(a.out[0], o, pe, L.x, a.positions, L.w, exp_depth(u.z), (uint64_t)v.x | ((uint64_t)v.y << 32),
-                     L.root, L.t);
-      write_child<T>(a.out[1], o, pp, L.x, a.positions, L.w, exp_depth(u.w), (uint64_t)v.z | ((uint64_t)v.w << 32),
-                     L.root, L.t);
+      write_child<T>(a.out_rec[0], a.out_pos[0], o, pe, L.x, a.positions, L.w, exp_depth_t<T>(u.z),
+                     (uint64_t)v.x | ((uint64_t)v.y << 32), L.root, L.t);
+      write_child<T>(a.out_rec[1], a.out_pos[1], o, pp, L.x, a.positions, L.w, exp_depth_t<T>(u.w),
+                     (uint64_t)v.z | ((uint64_t)v.w << 32), L.root, L.t);
     }
   }
   L.j = 1;
+  L.changed = true;
   return true;
 }
 
@@ -422,8 +485,8 @@ __global__ void __launch_bounds__(kStepThreads) k_count_lepton(StepArgs<T> a) {
     if (have && lepton_iter<T, false>(a, lt, L, q, 0)) {
       const int64_t i = a.begin + L.k;
       a.counts[L.k] = L.j;
-      if (a.src.nev) a.src.nev[i] = L.j;
-      if (L.j == 0) store_final<T>(a, L, a.push != 0);
+      if (a.from_main && a.src.nev) a.src.nev[i] = L.j;
+      if (L.j == 0) store_final<T>(a, L, a.push != 0, false);
       local_max = L.j > local_max ? L.j : local_max;
       capped |= L.capped;
       have = false;
@@ -448,14 +511,14 @@ __global__ void __launch_bounds__(kStepThreads) k_count_photon(StepArgs<T> a) {
     Lane<T> L;
     load_lane<T>(a, k, L);
     const int64_t i = a.begin + k;
-    if (a.src.alive[i] == 0) {  // a photon removed earlier is not processed
+    if (a.from_main && a.src.alive[i] == 0) {  // a photon removed earlier is not processed
       a.counts[k] = 0;
       continue;
     }
     photon_iter<T, false>(a, lt, L, 0);
     a.counts[k] = L.j;
-    if (a.src.nev) a.src.nev[i] = L.j;
-    if (L.j == 0) store_final<T>(a, L, false);
+    if (a.from_main && a.src.nev) a.src.nev[i] = L.j;
+    if (L.j == 0) store_final<T>(a, L, false, false);
     any_event |= L.j;
   }
   if (__any(any_event) && lane_id() == 0) atomicMax(&a.stats[kStatMaxEvents], 1ull);
@@ -570,7 +633,7 @@ __global__ void __launch_bounds__(kStepThreads) k_write_lepton(StepArgs<T> a) {
     }
     if (!__any(have)) break;
     if (have && lepton_iter<T, true>(a, lt, L, q, obase)) {
-      store_final<T>(a, L, true);
+      store_final<T>(a, L, true, false);
       have = false;
     }
   }
@@ -586,13 +649,7 @@ __global__ void __launch_bounds__(kStepThreads) k_write_photon(StepArgs<T> a) {
     Lane<T> L;
     load_lane<T>(a, k, L);
     photon_iter<T, true>(a, lt, L, a.offsets[k]);
-    const int64_t i = a.begin + k;
-    if (a.positions) {
-      a.src.x[i] = L.x[0];
-      a.src.y[i] = L.x[1];
-      a.src.z[i] = L.x[2];
-    }
-    a.src.alive[i] = 0;
+    store_final<T>(a, L, false, true);  // the photon is removed at its event
   }
 }
 
@@ -682,22 +739,40 @@ __global__ void __launch_bounds__(kMergeThreads) k_merge_photons(MergeArgs<T> a)
     const int64_t g = tile * kMergeTile + (int64_t)it * kMergeThreads + tid;
     bool ok = false;
     if (g < ntot) {
-      const bool in_main = g < a.n_main;
-      const SpeciesView<T>& s = in_main ? a.main : a.app;
-      const int64_t i = in_main ? g : g - a.n_main;
-      ok = s.alive[i] != 0;
-      if (ok) {
-        p[it][0] = s.px[i];
-        p[it][1] = s.py[i];
-        p[it][2] = s.pz[i];
-        if (a.positions) {
-          x[it][0] = s.x[i];
-          x[it][1] = s.y[i];
-          x[it][2] = s.z[i];
+      if (g < a.n_main) {
+        const SpeciesView<T>& s = a.main;
+        ok = s.alive[g] != 0;
+        if (ok) {
+          p[it][0] = s.px[g];
+          p[it][1] = s.py[g];
+          p[it][2] = s.pz[g];
+          if (a.positions) {
+            x[it][0] = s.x[g];
+            x[it][1] = s.y[g];
+            x[it][2] = s.z[g];
+          }
+          w[it] = s.w[g];
+          tau[it] = s.tau[g];
+          id[it] = s.id[g];
         }
-        w[it] = s.w[i];
-        tau[it] = s.tau[i];
-        id[it] = s.id[i];
+      } else {
+        const int64_t i = g - a.n_main;
+        Rec<T> r;
+        rec_load<T>(a.app, i, r);
+        ok = r.alive != 0;
+        if (ok) {
+          p[it][0] = r.px;
+          p[it][1] = r.py;
+          p[it][2] = r.pz;
+          if (a.positions) {
+            x[it][0] = a.app_pos[4 * i];
+            x[it][1] = a.app_pos[4 * i + 1];
+            x[it][2] = a.app_pos[4 * i + 2];
+          }
+          w[it] = r.w;
+          tau[it] = r.tau;
+          id[it] = r.id;
+        }
       }
     }
     okmask |= (ok ? 1u : 0u) << it;
@@ -768,6 +843,38 @@ __global__ void k_count_alive(const uint8_t* a, int64_t n, unsigned long long* o
   if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);
 }
 
+template <typename T>
+__global__ void k_count_alive_rec(const Rec<T>* rec, int64_t n, unsigned long long* out) {
+  int64_t c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += rec[i].alive != 0;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+// Appends n records after position `at` of a species' arrays (leptons: all
+// survive, so this is a plain conversion of the records).
+template <typename T>
+__global__ void k_append_records(SpeciesView<T> d, int64_t at, const Rec<T>* rec, const T* pos, int64_t n,
+                                 int positions) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    Rec<T> r;
+    rec_load<T>(rec, i, r);
+    const int64_t o = at + i;
+    d.px[o] = r.px;
+    d.py[o] = r.py;
+    d.pz[o] = r.pz;
+    d.w[o] = r.w;
+    d.tau[o] = r.tau;
+    d.id[o] = r.id;
+    if (positions) {
+      d.x[o] = pos[4 * i];
+      d.y[o] = pos[4 * i + 1];
+      d.z[o] = pos[4 * i + 2];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ explicit instantiations via launchers
 template <typename K, typename A>
 hipError_t launch_step_kernel(K kernel, const A& a, int grid, size_t lds, hipStream_t st) {
@@ -803,6 +910,23 @@ hipError_t launch_count_alive(const uint8_t* alive, int64_t n, unsigned long lon
   int grid = (int)((n + 255) / 256);
   grid = grid > 4096 ? 4096 : grid;
   hipLaunchKernelGGL(k_count_alive, dim3(grid), dim3(256), 0, st, alive, n, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_count_alive_rec(const Rec<T>* rec, int64_t n, unsigned long long* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int grid = (int)((n + 255) / 256);
+  grid = grid > 4096 ? 4096 : grid;
+  hipLaunchKernelGGL(k_count_alive_rec<T>, dim3(grid), dim3(256), 0, st, rec, n, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_append_records(const SpeciesView<T>& dst, int64_t at, const Rec<T>* rec, const T* pos, int64_t n,
+                                 int positions, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int grid = (int)((n + 255) / 256);
+  grid = grid > 8192 ? 8192 : grid;
+  hipLaunchKernelGGL(k_append_records<T>, dim3(grid), dim3(256), 0, st, dst, at, rec, pos, n, positions);
   return hipGetLastError();
 }
 template <typename T>
@@ -846,6 +970,12 @@ template hipError_t launch_write<double, true>(const StepArgs<double>&, int, siz
 template hipError_t launch_merge_photons<float>(const MergeArgs<float>&, hipStream_t);
 template hipError_t launch_merge_photons<double>(const MergeArgs<double>&, hipStream_t);
 template hipError_t launch_init_tau<float>(double*, const uint64_t*, int64_t, uint64_t, uint32_t, hipStream_t);
+template hipError_t launch_count_alive_rec<float>(const Rec<float>*, int64_t, unsigned long long*, hipStream_t);
+template hipError_t launch_count_alive_rec<double>(const Rec<double>*, int64_t, unsigned long long*, hipStream_t);
+template hipError_t launch_append_records<float>(const SpeciesView<float>&, int64_t, const Rec<float>*, const float*,
+                                                 int64_t, int, hipStream_t);
+template hipError_t launch_append_records<double>(const SpeciesView<double>&, int64_t, const Rec<double>*,
+                                                  const double*, int64_t, int, hipStream_t);
 template hipError_t launch_eval_rate<float>(const TableView&, int, const float*, const float*, float*, int64_t,
                                             hipStream_t);
 template hipError_t launch_eval_rate<double>(const TableView&, int, const double*, const double*, double*, int64_t,

@@ -35,7 +35,7 @@ def run_gpu(sf, torch, tabs, wl, inputs, dtype, cap, cfg, seed=0, step_index=0, 
         main.append(sf.Store.from_arrays(d["p"], d["w"], d["tau"], d["id"], dtype=dtype, photon=s == 2,
                                          capacity=max(n, 1), x=np.zeros((n, 3)) if positions else None))
         fields.append(sf.Fields.from_array(d["fields"] if d["fields"].shape[0] else np.zeros((1, 6)), dtype))
-        app.append(sf.Store.empty(cap[s], dtype, photon=s == 2, append=True, positions=positions))
+        app.append(sf.AppendBuffer(cap[s], dtype, positions=positions))
     rc, st = sf.step(tabs, main, fields, app, wl.dt, seed, step_index, cfg, check=False)
     torch.cuda.synchronize()
     return rc, st, main, fields, app

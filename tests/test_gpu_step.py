@@ -233,18 +233,18 @@ def test_capacity_overflow(env):
             sf.Store.empty(1, torch.float32), sf.Store.empty(1, torch.float32, photon=True)]
     fields = [sf.Fields.from_array(inp[0]["fields"]), sf.Fields.from_array(np.zeros((1, 6))),
               sf.Fields.from_array(np.zeros((1, 6)))]
-    app = [sf.Store.empty(4, torch.float32, append=True), sf.Store.empty(4, torch.float32, append=True),
-           sf.Store.empty(64, torch.float32, photon=True, append=True)]
-    app[2].px.fill_(12345.0)
-    app[2].cap = 50  # the library may use 50 of the 64 slots
+    app = [sf.AppendBuffer(4), sf.AppendBuffer(4), sf.AppendBuffer(64)]
+    app[2].data.fill_(0xAB)
+    app[2].cap = 50  # the library may use 50 of the 64 records
     rc, st = sf.step(tabs, main, fields, app, wl.dt, 0, 0, sf.step_cfg(pair=False, push=False), check=False)
     torch.cuda.synchronize()
     assert rc == 2, rc
     print(f"overflow: required photons {st.required_capacity[2]} > capacity 50")
     assert st.required_capacity[2] > 50
     assert app[2].count == 50
-    assert torch.all(app[2].px[50:] == 12345.0)
-    assert not torch.any(app[2].px[:50] == 12345.0)
+    rs = app[2].rec_dtype.itemsize
+    assert torch.all(app[2].data[50 * rs:] == 0xAB)
+    assert not torch.all(app[2].data[49 * rs:50 * rs] == 0xAB)
 
 
 def test_init_tau_parity(env, orc):
