@@ -87,6 +87,7 @@ def lib():
             ("orc_sample_pair", None, [p, p, i64, p, p]),
             ("orc_sample_rad_r", None, [d, d, d, C.c_int, p, p]),
             ("orc_sample_pair_r", None, [d, d, d, C.c_int, p, p]),
+            ("orc_sample_rad_grid", None, [p, i64, p, p, i64, p, p]),
             ("orc_chi", d, [p, d, p, p]),
             ("orc_boris", None, [p, d, p, p, d]),
             ("orc_init_tau", None, [C.POINTER(Species), C.c_uint64, C.c_uint32]),
@@ -219,6 +220,19 @@ def sample_rad_r2(chi: float, r: float, rc: float) -> tuple[float, float]:
     o = C.c_double()
     lib().orc_sample_rad_r(chi, r, rc, 0, C.byref(d), C.byref(o))
     return d.value, o.value
+
+
+def sample_rad_grid(chi, r, rc=None) -> tuple[np.ndarray, np.ndarray]:
+    """Emission draws on a chi grid: chi [m], r and rc = 1 - r [m, k] -> delta and 1 - delta [m, k]."""
+    chi = np.ascontiguousarray(chi, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    rc = np.ascontiguousarray(1.0 - r if rc is None else rc, dtype=np.float64)
+    m, k = r.shape
+    assert chi.shape == (m,) and rc.shape == r.shape
+    d = np.empty_like(r)
+    o = np.empty_like(r)
+    lib().orc_sample_rad_grid(_ptr(chi), m, _ptr(r), _ptr(rc), k, _ptr(d), _ptr(o))
+    return d, o
 
 
 def sample_pair_r(chi: float, r: float, definition: bool = False, rc: float | None = None) -> float:

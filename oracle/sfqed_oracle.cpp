@@ -440,37 +440,66 @@ double invert_in_panel(const F& f, double a, double b, double target, double pan
   return x;
 }
 
+// The accepted panels of one spectrum with their running sums from the bottom
+// (lo[k] = panels 0..k) and from the top (hi[k] = panels k..end), accumulated in
+// the order a sequential scan would use.
+struct CdfPanels {
+  std::vector<Panel> ps;
+  std::vector<double> lo, hi;
+  double tot = 0.0;
+};
+
+template <class F>
+CdfPanels cdf_panels(const F& f, const std::vector<double>& breaks) {
+  CdfPanels c;
+  c.ps = quad_panels(f, breaks, kRtol, 0.0);
+  const size_t n = c.ps.size();
+  c.lo.resize(n);
+  c.hi.resize(n);
+  double cum = 0.0;
+  for (size_t k = 0; k < n; ++k) c.lo[k] = cum += c.ps[k].val();
+  c.tot = cum;
+  cum = 0.0;
+  for (size_t k = n; k-- > 0;) c.hi[k] = cum += c.ps[k].val();
+  return c;
+}
+
 // Returns x with int_0^x f = r * total, using the complement from the top end
-// when r > 1/2 (rc = 1 - r exact).
+// when r > 1/2 (rc = 1 - r exact).  The panel is the first one (from the
+// respective end) whose running sum reaches the target.
+template <class F>
+double invert_cdf(const F& f, const CdfPanels& c, double r, double rc) {
+  if (!(c.tot > 0.0)) return 0.0;
+  const size_t n = c.ps.size();
+  if (r <= 0.5) {
+    const double target = r * c.tot;
+    const size_t k = std::lower_bound(c.lo.begin(), c.lo.end(), target) - c.lo.begin();
+    if (k == n) return c.ps.back().b;
+    const Panel& p = c.ps[k];
+    return invert_in_panel(f, p.a, p.b, target - (k > 0 ? c.lo[k - 1] : 0.0), p.val());
+  }
+  // from the top: find x with int_x^end f = rc * tot
+  const double target = rc * c.tot;
+  // hi is non-increasing in k: the largest k with hi[k] >= target
+  size_t lo = 0, hi = n;
+  while (lo < hi) {
+    const size_t mid = (lo + hi) / 2;
+    if (c.hi[mid] >= target) lo = mid + 1; else hi = mid;
+  }
+  if (lo == 0) return c.ps.front().a;
+  const size_t k = lo - 1;
+  const Panel& p = c.ps[k];
+  // int_{p.a}^{x} f = p.val - (target - cum), cum = sum of the panels above k
+  const double cum = k + 1 < n ? c.hi[k + 1] : 0.0;
+  return invert_in_panel(f, p.a, p.b, p.val() - (target - cum), p.val());
+}
+
 template <class F>
 double invert_cdf(const F& f, const std::vector<double>& breaks, double r, double rc,
                   double* total_out) {
-  const std::vector<Panel> ps = quad_panels(f, breaks, kRtol, 0.0);
-  double tot = 0.0;
-  for (const Panel& p : ps) tot += p.val();
-  if (total_out) *total_out = tot;
-  if (!(tot > 0.0)) return 0.0;
-  if (r <= 0.5) {
-    const double target = r * tot;
-    double cum = 0.0;
-    for (const Panel& p : ps) {
-      if (cum + p.val() >= target) return invert_in_panel(f, p.a, p.b, target - cum, p.val());
-      cum += p.val();
-    }
-    return ps.back().b;
-  }
-  // from the top: find x with int_x^end f = rc * tot
-  const double target = rc * tot;
-  double cum = 0.0;
-  for (size_t k = ps.size(); k-- > 0;) {
-    const Panel& p = ps[k];
-    if (cum + p.val() >= target) {
-      // int_{p.a}^{x} f = p.val - (target - cum)
-      return invert_in_panel(f, p.a, p.b, p.val() - (target - cum), p.val());
-    }
-    cum += p.val();
-  }
-  return ps.front().a;
+  const CdfPanels c = cdf_panels(f, breaks);
+  if (total_out) *total_out = c.tot;
+  return invert_cdf(f, c, r, rc);
 }
 
 // Inverse CDF of the emission spectrum: returns delta and 1 - delta.
@@ -651,6 +680,24 @@ void orc_sample_rad(const double* chi, const uint32_t* k, int64_t n, double* d, 
 void orc_sample_pair(const double* chi, const uint32_t* k, int64_t n, double* xi, double* omx) {
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t i = 0; i < n; ++i) sample_pair(chi[i], u01(k[i]), u01c(k[i]), false, xi + i, omx + i);
+}
+
+// Emission draws on a chi grid: for chi[i] the spectrum's panels are built
+// once and r[i*k + j], j < k, are inverted (rc = 1 - r exact).  Same values as
+// orc_sample_rad_r with the fast tier.
+void orc_sample_rad_grid(const double* chi, int64_t m, const double* r, const double* rc, int64_t k, double* d,
+                         double* omd) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < m; ++i) {
+    const RadVar f{chi[i], false};
+    const CdfPanels c = cdf_panels(f, rad_breaks(chi[i]));
+    for (int64_t j = i * k; j < (i + 1) * k; ++j) {
+      const double v = invert_cdf(f, c, r[j], rc[j]);
+      const double z = 1.5 * chi[i] * v * v * v;
+      d[j] = z / (1.0 + z);
+      omd[j] = 1.0 / (1.0 + z);
+    }
+  }
 }
 
 // Same with a general r in (0,1) (rc = 1 - r), definitions or fast tier.

@@ -224,6 +224,16 @@ def sampler(n: int, seed: int = 0, chi_range=(1e-2, 1e2), indices=None):
     return chi, bits32(seed, 41, idx)
 
 
+def surrogate_draws(groups, per_group: int, seed: int = 0, chi_range=(1e-2, 1e2)):
+    """Inputs of the surrogate's training and evaluation draws: for each group
+    index g, chi_g log-uniform in chi_range (rounded to float32, the precision
+    the sampler receives) and per_group raw 32-bit uniforms k[g, j]."""
+    g = np.asarray(groups, dtype=np.uint64)
+    chi = log_uniform(uniform(seed, 42, g), *chi_range).astype(np.float32)
+    j = (g[:, None] * np.uint64(per_group) + np.arange(per_group, dtype=np.uint64)[None, :]).ravel()
+    return chi, bits32(seed, 43, j).reshape(g.size, per_group)
+
+
 def static_b_sweep(n: int = 200_000_000, seed: int = 0, indices=None, chi_range=(1e-3, 1e3),
                    energy_range=(1e2, 1e4)) -> Workload:
     half = n // 2
