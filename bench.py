@@ -104,6 +104,48 @@ def sum_stats(stats: list) -> dict:
     return out
 
 
+# ----------------------------------------------------------------------------- surrogate vs table
+def surrogate_comparison(sf, torch, tables, n: int = 100_000_000, reps: int = 3) -> dict:
+    """Emission sampling of n events (chi log-uniform in [1e-2, 1e2], 32-bit
+    uniforms) by the FP32 table and by the trained BF16-MFMA network; the
+    spectral error of each is the paired L1 against the FP64 table on the same
+    events (256 bins of log10 delta in [-12, 0])."""
+    import numpy as np
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4242)
+    chi = torch.exp(torch.empty(n, device="cuda").uniform_(float(np.log(1e-2)), float(np.log(1e2)), generator=g))
+    k = torch.randint(-2**31, 2**31 - 1, (n,), dtype=torch.int32, device="cuda", generator=g)
+    net = sf.Mlp(sf.load_surrogate())
+
+    def timed(fn):
+        out = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps
+
+    d_tab, ms_tab = timed(lambda: sf.sample(tables, 0, chi, k))
+    d_mlp, ms_mlp = timed(lambda: net.sample(tables, chi, k))
+    d_ref = sf.sample(tables, 0, chi.double(), k)
+
+    def hist(d):
+        return torch.histc(torch.log10(d.double()), bins=256, min=-12.0, max=0.0)
+
+    h_ref = hist(d_ref)
+    l1_tab = float((hist(d_tab) - h_ref).abs().sum()) / n
+    l1_mlp = float((hist(d_mlp) - h_ref).abs().sum()) / n
+    flop = 2 * (2 * 64 + 64 * 64 + 64)  # per event, the network as specified
+    return {"events": n, "table_fp32_events_per_s": n / (ms_tab * 1e-3), "mlp_bf16_events_per_s": n / (ms_mlp * 1e-3),
+            "speedup_mlp_over_table": ms_tab / ms_mlp, "table_ms": ms_tab, "mlp_ms": ms_mlp,
+            "l1_vs_fp64_table": {"table_fp32": l1_tab, "mlp_bf16": l1_mlp},
+            "mlp_mfma_tflops": flop * n / (ms_mlp * 1e-3) / 1e12, "mlp_mfma_peak_tflops": 2500.0,
+            "target": {"speedup": 1.5, "l1": 1e-3, "met": bool(ms_tab / ms_mlp >= 1.5 and l1_mlp <= 1e-3)}}
+
+
 # ----------------------------------------------------------------------------- CPU baseline
 def cpu_baseline(wl_fn, full_n, stride, gamma_min):
     """The FP64 oracle on a strided sample of the same workload (FP32-rounded inputs)."""
@@ -141,6 +183,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--cpu-stride", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--gamma-min", type=float, default=2.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM counters)")
@@ -240,6 +283,11 @@ def main(argv=None):
            "roofline": roof,
            "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                        for k, v in kern.items()}}
+    if not args.no_surrogate:
+        del dw
+        torch.cuda.empty_cache()
+        log("surrogate vs table: 1e8 emission events")
+        out["surrogate"] = surrogate_comparison(sf, torch, tables)
     if not args.no_cpu:
         log("CPU baseline: the FP64 oracle on a strided sample")
         out["cpu_baseline"] = cpu_baseline(synth.crossed_field, args.n, args.cpu_stride, args.gamma_min)

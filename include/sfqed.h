@@ -235,6 +235,82 @@ qed_status qed_eval_particles(const qed_tables *t, int species, qed_dtype dtype,
 qed_status qed_sample(const qed_tables *t, int process, qed_dtype dtype, const void *chi, const uint32_t *k,
                       void *out, int64_t n, void *stream);
 
+/* ------------------------------------------------------------------ surrogate
+ * A learned replacement of the emission inverse CDF (the two-dimensional table
+ * in chi and energy fraction of Sec. 3): a 2 -> 64 -> 64 -> 1 perceptron with
+ * SiLU activations maps x1 = ln(chi) f1_scale + f1_shift and x2 = logit(r)
+ * f2_scale to y, and delta = sigmoid(out_scale y + ln chi).  Layer 2 (and its
+ * backward) multiplies BF16 weights by BF16 activations with FP32
+ * accumulation (MFMA); layers 1 and 3 are FP32.  Inside [chi_min, chi_max] the
+ * network samples; outside it the FP32 table does (the fallback).
+ *
+ * Parameters are 4417 FP32 numbers in the order W1[64][2], b1[64],
+ * W2[64][64] (row = output), b2[64], w3[64], b3.  Training minimises the mean
+ * squared error of y against targets with Adam (FP32 master weights, FP32
+ * moments), entirely on the device; per-wave partial gradients are summed in a
+ * fixed order, so results do not depend on scheduling.
+ * A qed_mlp belongs to the device current at qed_mlp_create; its calls must
+ * run with that device current.  Calls that overlap on one qed_mlp race. */
+#define QED_MLP_PARAMS 4417
+typedef struct qed_mlp qed_mlp;
+
+typedef struct {
+  float chi_min, chi_max;     /* trained range (the table samples outside) */
+  float f1_scale, f1_shift;   /* x1 = ln(chi) f1_scale + f1_shift */
+  float f2_scale;             /* x2 = logit(r) f2_scale */
+  float out_scale;            /* q = out_scale y = logit(delta) - ln chi */
+} qed_mlp_cfg;
+
+/* chi in [1e-2, 1e2], x1 = ln chi / ln 100, x2 = logit(r) / 10, q = 10 y. */
+void qed_mlp_cfg_default(qed_mlp_cfg *cfg);
+
+/* Allocates the network (all parameters zero) on the current device. */
+qed_status qed_mlp_create(const qed_mlp_cfg *cfg, qed_mlp **out);
+void qed_mlp_free(qed_mlp *m);
+qed_status qed_mlp_get_cfg(const qed_mlp *m, qed_mlp_cfg *cfg);
+
+/* Host copies of the FP32 parameters (QED_MLP_PARAMS floats).  set also
+ * resets the Adam moments and step count.  Both wait for the stream. */
+qed_status qed_mlp_set_params(qed_mlp *m, const float *params, void *stream);
+qed_status qed_mlp_get_params(const qed_mlp *m, float *params, void *stream);
+
+/* y[i] = network output for inputs x[i] = (x1, x2); device arrays x [n][2]
+ * and y [n]. */
+qed_status qed_mlp_forward(const qed_mlp *m, const float *x, float *y, int64_t n, void *stream);
+
+/* Gradient (device, QED_MLP_PARAMS floats, parameter order) and value (device,
+ * one float) of L = mean over i of (y(x_i) - t_i)^2, for device arrays
+ * x [n][2] and t [n]; n >= 1. */
+qed_status qed_mlp_grad(qed_mlp *m, const float *x, const float *t, int64_t n, float *grad, float *loss,
+                        void *stream);
+
+typedef struct {
+  int64_t steps, batch;       /* Adam steps of this call and samples per step (batch <= n) */
+  int64_t schedule_start;     /* index of this call's first step in the schedule (for chunked runs) */
+  int64_t schedule_len;       /* length of the schedule; 0: steps */
+  float lr_max, lr_min;       /* linear warm-up to lr_max over warmup * schedule_len, then cosine to lr_min */
+  float warmup;
+  float beta1, beta2, eps;
+  uint64_t seed;              /* batch sampling (Philox, counter = schedule step) */
+  int32_t shuffle;            /* 1: batches of independent uniform draws of the data index;
+                                 0: consecutive batches cycling through the data in order */
+} qed_mlp_train_cfg;
+
+void qed_mlp_train_cfg_default(qed_mlp_train_cfg *cfg);
+
+/* Trains on device data x [n][2], t [n]: `steps` Adam steps continuing from
+ * the current parameters and moments.  loss (device, steps floats, or NULL)
+ * receives each step's batch loss before its update.  Asynchronous on the
+ * stream; the network's scratch grows with the batch (hipMalloc). */
+qed_status qed_mlp_train(qed_mlp *m, const float *x, const float *t, int64_t n, const qed_mlp_train_cfg *cfg,
+                         float *loss, void *stream);
+
+/* Emission energy fractions delta (FP32, device) for chi and raw uniforms k
+ * (r = (k + 1/2) / 2^32): the network inside its chi range, the FP32 table of
+ * `t` outside it. */
+qed_status qed_sample_mlp(const qed_tables *t, const qed_mlp *m, const float *chi, const uint32_t *k, float *delta,
+                          int64_t n, void *stream);
+
 /* Grid geometry of built tables (21 doubles): nseg_rad, s_lo_rad, nseg_pair,
  * s_lo_pair, hermite_nodes, then per process (emission, pairs): rows32,
  * cols32, rows64, cols64, s_first, s_last, x_first, x_last. */

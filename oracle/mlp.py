@@ -7,11 +7,13 @@ order W1 [64, 2], b1 [64], W2 [64, 64] (out, in), b2 [64], w3 [64], b3 [1]
 the tests pin the backward to the forward by finite differences.
 
 bf16=True rounds the operands of the BF16 matrix products to bfloat16 and
-keeps everything else in FP64: in the forward pass W2 and the layer-1
-activations; in the backward pass the operands of W2^T dz2 and of the weight
-gradients (dz2, dz1, h1, h2, the inputs, dy).  This is the arithmetic of a
-BF16-weight network with wide accumulation; the gradient is then the one of
-the rounded forward with rounding treated as the identity.
+keeps everything else in FP64: in the forward pass W2 is rounded and each
+layer-1 activation h enters layer 2 as hi + lo with hi = bf16(h),
+lo = bf16(h - hi) (about 16 significant bits); in the backward pass the
+operands of W2^T dz2 and of the weight gradients (dz2, dz1, hi, h2, the
+inputs, dy) are rounded.  This is the arithmetic of a BF16-weight network
+with wide accumulation; the gradient is then the one of the rounded forward
+with rounding treated as the identity.
 """
 from __future__ import annotations
 
@@ -52,9 +54,12 @@ def forward(p, X, bf16=False):
     z1 = X @ W1.T + b1
     h1 = silu(z1)
     if bf16:
-        h1 = bf16_round(h1)
+        hi = bf16_round(h1)
         W2 = bf16_round(W2)
-    z2 = h1 @ W2.T + b2
+        z2 = (hi + bf16_round(h1 - hi)) @ W2.T + b2
+        h1 = hi
+    else:
+        z2 = h1 @ W2.T + b2
     h2 = silu(z2)
     y = h2 @ w3 + b3
     return y, (X, z1, h1, z2, h2)
@@ -72,7 +77,7 @@ def loss_grad(p, X, t, bf16=False):
     g_w3 = rd(h2).T @ rd(dy)
     g_b3 = dy.sum()
     dz2 = (dy[:, None] * w3[None, :]) * dsilu(z2)
-    g_W2 = rd(dz2).T @ h1                 # h1 is already rounded when bf16
+    g_W2 = rd(dz2).T @ h1                 # h1 is its leading bfloat16 part when bf16
     g_b2 = rd(dz2).sum(axis=0)
     dz1 = (rd(dz2) @ rd(W2)) * dsilu(z1)
     g_W1 = rd(dz1).T @ rd(X)

@@ -91,6 +91,20 @@ class StepStats(C.Structure):
 _lib = None
 
 
+MLP_PARAMS = 4417
+
+
+class MlpCfg(C.Structure):
+    _fields_ = [(k, C.c_float) for k in ("chi_min", "chi_max", "f1_scale", "f1_shift", "f2_scale", "out_scale")]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("batch", C.c_int64), ("schedule_start", C.c_int64),
+                ("schedule_len", C.c_int64), ("lr_max", C.c_float), ("lr_min", C.c_float),
+                ("warmup", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("seed", C.c_uint64), ("shuffle", C.c_int32)]
+
+
 def lib():
     """The loaded libsfqed (raises SfqedError if it has not been built)."""
     global _lib
@@ -113,6 +127,17 @@ def lib():
             "qed_eval_rate": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
             "qed_eval_particles": (C.c_int, [v, C.c_int, C.c_int, p, p, p, C.POINTER(CFields), i64, p, p, v]),
             "qed_sample": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
+            "qed_mlp_cfg_default": (None, [C.POINTER(MlpCfg)]),
+            "qed_mlp_train_cfg_default": (None, [C.POINTER(TrainCfg)]),
+            "qed_mlp_create": (C.c_int, [C.POINTER(MlpCfg), C.POINTER(v)]),
+            "qed_mlp_free": (None, [v]),
+            "qed_mlp_get_cfg": (C.c_int, [v, C.POINTER(MlpCfg)]),
+            "qed_mlp_set_params": (C.c_int, [v, p, v]),
+            "qed_mlp_get_params": (C.c_int, [v, p, v]),
+            "qed_mlp_forward": (C.c_int, [v, p, p, i64, v]),
+            "qed_mlp_grad": (C.c_int, [v, p, p, i64, p, p, v]),
+            "qed_mlp_train": (C.c_int, [v, p, p, i64, C.POINTER(TrainCfg), p, v]),
+            "qed_sample_mlp": (C.c_int, [v, v, p, p, p, i64, v]),
             "qed_status_str": (C.c_char_p, [C.c_int]),
             "qed_last_error": (C.c_char_p, []),
             "qed_abi_version": (C.c_int32, []),
@@ -428,3 +453,101 @@ def sample(tables: Tables, process: int, chi, k, stream=None):
     _check(lib().qed_sample(tables.handle, process, _dtype_code(chi.dtype), _ptr(chi), _ptr(k), _ptr(out),
                             chi.numel(), _stream(stream)))
     return out
+
+
+# ----------------------------------------------------------------------------- surrogate
+def mlp_cfg(**overrides) -> MlpCfg:
+    cfg = MlpCfg()
+    lib().qed_mlp_cfg_default(C.byref(cfg))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def train_cfg(**overrides) -> TrainCfg:
+    cfg = TrainCfg()
+    lib().qed_mlp_train_cfg_default(C.byref(cfg))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Mlp:
+    """The inverse-CDF surrogate network on the current device (qed_mlp)."""
+
+    def __init__(self, params=None, cfg: MlpCfg | None = None, **cfg_overrides):
+        h = C.c_void_p()
+        self.cfg = cfg if cfg is not None else mlp_cfg(**cfg_overrides)
+        _check(lib().qed_mlp_create(C.byref(self.cfg), C.byref(h)))
+        self.handle = h
+        if params is not None:
+            self.set_params(params)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qed_mlp_free(h)
+            self.handle = None
+
+    def set_params(self, params, stream=None):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        assert a.shape == (MLP_PARAMS,), a.shape
+        _check(lib().qed_mlp_set_params(self.handle, a.ctypes.data_as(C.c_void_p), _stream(stream)))
+
+    def params(self, stream=None) -> np.ndarray:
+        a = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(lib().qed_mlp_get_params(self.handle, a.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return a
+
+    def forward(self, x, stream=None):
+        """Network outputs for a device float32 tensor x [n, 2]."""
+        torch = _torch()
+        assert x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 2
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(lib().qed_mlp_forward(self.handle, _ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+        return y
+
+    def grad(self, x, t, stream=None):
+        """(gradient [4417], loss) of the mean squared error on device tensors x [n, 2], t [n]."""
+        torch = _torch()
+        assert x.dtype == torch.float32 and t.dtype == torch.float32 and x.is_contiguous() and t.is_contiguous()
+        assert x.dim() == 2 and x.shape[1] == 2 and t.shape == (x.shape[0],)
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(lib().qed_mlp_grad(self.handle, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss), _stream(stream)))
+        return g, loss
+
+    def train(self, x, t, cfg: TrainCfg, record_loss=True, stream=None):
+        """cfg.steps Adam steps on device data; returns the per-step loss tensor (or None)."""
+        torch = _torch()
+        assert x.dtype == torch.float32 and t.dtype == torch.float32 and x.is_contiguous() and t.is_contiguous()
+        assert x.dim() == 2 and x.shape[1] == 2 and t.shape == (x.shape[0],)
+        loss = torch.empty(max(cfg.steps, 1), dtype=torch.float32, device=x.device) if record_loss else None
+        _check(lib().qed_mlp_train(self.handle, _ptr(x), _ptr(t), x.shape[0], C.byref(cfg), _ptr(loss),
+                                   _stream(stream)))
+        return loss
+
+    def sample(self, tables: "Tables", chi, k, stream=None):
+        """Emission delta for float32 chi and raw uniforms k (int32 tensor holding the bits)."""
+        torch = _torch()
+        assert chi.dtype == torch.float32 and chi.is_contiguous() and k.is_contiguous() and k.numel() == chi.numel()
+        out = torch.empty_like(chi)
+        _check(lib().qed_sample_mlp(tables.handle, self.handle, _ptr(chi), _ptr(k), _ptr(out), chi.numel(),
+                                    _stream(stream)))
+        return out
+
+    def features(self, chi, r=None, logit_r=None):
+        """Network inputs for chi and r (numpy, float64 arithmetic)."""
+        chi = np.asarray(chi, dtype=np.float64)
+        if logit_r is None:
+            r = np.asarray(r, dtype=np.float64)
+            logit_r = np.log(r) - np.log1p(-r)
+        return np.stack([np.log(chi) * self.cfg.f1_scale + self.cfg.f1_shift,
+                         np.asarray(logit_r) * self.cfg.f2_scale], axis=1)
+
+
+def load_surrogate(path=None) -> np.ndarray:
+    """Trained parameters shipped with the package (surrogate_rad.npz)."""
+    path = Path(path) if path is not None else Path(__file__).resolve().parent / "surrogate_rad.npz"
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"].astype(np.float32)

@@ -1,0 +1,176 @@
+"""GPU parity of the surrogate network's kernels (qed_mlp_*) against the FP64
+oracle of oracle/mlp.py, which rounds the operands of the BF16 products the
+same way (W2 and the layer-1 activations forward; the MFMA operands backward).
+
+Tolerances.  With identical roundings the remaining difference is FP32
+accumulation and the hardware exp/reciprocal of the SiLU, about 1e-6 on O(1)
+outputs.  An FP32 value within ~1e-7 relative of a bfloat16 rounding boundary can
+round the other way than in FP64 (probability ~2.5e-5 per operand); such a flip
+moves one operand by one bfloat16 step (2^-8 relative), which bounds the rare
+larger differences.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+
+from gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def rand_params(seed, scale=0.35):
+    g = np.random.default_rng(seed)
+    p = g.normal(scale=scale, size=omlp.N_PARAMS)
+    return p.astype(np.float32).astype(np.float64)
+
+
+def rand_inputs(seed, n):
+    g = np.random.default_rng(seed)
+    X = np.stack([g.uniform(-1.0, 1.0, n), g.uniform(-2.3, 2.3, n)], 1)
+    return X.astype(np.float32).astype(np.float64)
+
+
+def flip_bound(p, X):
+    """Per-sample bound on |dy| from one-step bfloat16 flips of every layer-1 activation."""
+    W1, b1, W2, b2, w3, b3 = omlp.unpack(p)
+    h1 = omlp.silu(X @ W1.T + b1)
+    # |silu'| <= 1.1
+    return 1.1 * (np.abs(h1) * 2.0**-8) @ (np.abs(omlp.bf16_round(W2)).T @ np.abs(w3))
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 1000, 4133])
+def test_forward_parity(n):
+    torch, sf = need_gpu()
+    p = rand_params(1)
+    X = rand_inputs(2, n)
+    net = sf.Mlp(p)
+    y = net.forward(torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
+    yo, _ = omlp.forward(p, X, bf16=True)
+    err = np.abs(y - yo)
+    tight = err <= 1e-5 * (1 + np.abs(yo))
+    assert tight.mean() >= 0.99 if n >= 100 else tight.all() or (err <= 1e-5 + flip_bound(p, X)).all()
+    assert (err <= 1e-5 * (1 + np.abs(yo)) + flip_bound(p, X)).all(), err.max()
+    # and against the unrounded network, within the bfloat16 effect
+    y64, _ = omlp.forward(p, X)
+    assert np.abs(y - y64).max() < 0.05 * (1 + np.abs(y64).max())
+
+
+def test_mfma_layout_single_feature():
+    """One nonzero W2 entry at a time: y depends on exactly that (out, in) pair,
+    so a wrong operand or result layout shows up as a wrong or missing term."""
+    torch, sf = need_gpu()
+    g = np.random.default_rng(5)
+    X = rand_inputs(6, 64)
+    Xt = torch.tensor(X, dtype=torch.float32, device="cuda")
+    for f, k in [(0, 0), (1, 0), (0, 1), (5, 9), (31, 32), (32, 31), (63, 63), (17, 50), (40, 3)]:
+        W1 = g.normal(size=(64, 2))
+        b1 = g.normal(size=64)
+        W2 = np.zeros((64, 64))
+        W2[f, k] = 1.5
+        b2 = np.zeros(64)
+        w3 = np.zeros(64)
+        w3[f] = 1.0
+        p = omlp.pack(W1, b1, W2, b2, w3, 0.25).astype(np.float32).astype(np.float64)
+        net = sf.Mlp(p)
+        y = net.forward(Xt).cpu().numpy()
+        yo, _ = omlp.forward(p, X, bf16=True)
+        np.testing.assert_allclose(y, yo, rtol=1e-5, atol=1e-6, err_msg=f"W2[{f},{k}]")
+
+
+@pytest.mark.parametrize("n", [32, 1000])
+def test_gradient_parity(n):
+    torch, sf = need_gpu()
+    p = rand_params(3, scale=0.3)
+    X = rand_inputs(4, n)
+    t = np.random.default_rng(7).normal(size=n).astype(np.float32).astype(np.float64)
+    net = sf.Mlp(p)
+    g, loss = net.grad(torch.tensor(X, dtype=torch.float32, device="cuda"),
+                       torch.tensor(t, dtype=torch.float32, device="cuda"))
+    g = g.cpu().numpy().astype(np.float64)
+    Lo, go = omlp.loss_grad(p, X, t, bf16=True)
+    assert abs(loss.item() - Lo) <= 1e-5 * Lo
+    # per parameter block, relative to the block's norm
+    offs = [0, 128, 192, 4288, 4352, 4416, 4417]
+    for a, b in zip(offs[:-1], offs[1:]):
+        d = np.linalg.norm(g[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-30)
+        assert d <= 2e-3, (a, b, d)
+    # the mixed-precision gradient still points where the FP64 one does
+    L64, g64 = omlp.loss_grad(p, X, t)
+    cos = g @ g64 / (np.linalg.norm(g) * np.linalg.norm(g64))
+    assert cos > 0.999, cos
+
+
+def test_adam_steps():
+    """Two Adam steps on one full batch against numpy, from the GPU's own gradients."""
+    torch, sf = need_gpu()
+    n = 512
+    p0 = rand_params(8, scale=0.3).astype(np.float32)
+    X = torch.tensor(rand_inputs(9, n), dtype=torch.float32, device="cuda")
+    t = torch.tensor(np.random.default_rng(10).normal(size=n), dtype=torch.float32, device="cuda")
+    net = sf.Mlp(p0)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    cfg = sf.train_cfg(steps=1, batch=n, lr_max=lr, lr_min=lr, warmup=0.0, beta1=b1, beta2=b2, eps=eps, shuffle=0)
+    p = p0.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for step in (1, 2):
+        g, _ = net.grad(X, t)
+        g = g.cpu().numpy().astype(np.float64)
+        net.train(X, t, cfg)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        p = p - lr * (m / (1 - b1**step)) / (np.sqrt(v / (1 - b2**step)) + eps)
+        got = net.params().astype(np.float64)
+        np.testing.assert_allclose(got, p, rtol=0, atol=2e-6 * step)
+
+
+def test_training_is_deterministic_and_learns():
+    torch, sf = need_gpu()
+    n = 1 << 16
+    teacher = rand_params(11, scale=0.25)
+    X = rand_inputs(12, n)
+    tgt, _ = omlp.forward(teacher, X)
+    Xt = torch.tensor(X, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(tgt, dtype=torch.float32, device="cuda")
+    init = rand_params(13, scale=0.1).astype(np.float32)
+    cfg = sf.train_cfg(steps=1500, batch=4096, lr_max=3e-3, lr_min=1e-5, seed=3)
+    runs = []
+    for _ in range(2):
+        net = sf.Mlp(init)
+        loss = net.train(Xt, tt, cfg).cpu().numpy()
+        runs.append((net.params(), loss))
+    assert np.array_equal(runs[0][0], runs[1][0]), "training is not bit-reproducible"
+    loss = runs[0][1]
+    assert np.isfinite(loss).all()
+    assert loss[-50:].mean() < 1e-2 * loss[:10].mean(), (loss[:10].mean(), loss[-50:].mean())
+    # the recorded loss is the mean squared error of the parameters before each step
+    net = sf.Mlp(runs[0][0])
+    y = net.forward(Xt).cpu().numpy()
+    assert np.mean((y - tgt) ** 2) < 1e-2 * loss[:10].mean()
+
+
+def test_sampler_fallback_and_inside():
+    torch, sf = need_gpu()
+    tabs = sf.Tables()
+    p = rand_params(14, scale=0.2)
+    net = sf.Mlp(p)
+    g = np.random.default_rng(15)
+    n = 5000
+    chi = np.exp(g.uniform(np.log(1e-4), np.log(1e4), n)).astype(np.float32)
+    k = g.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    chit = torch.tensor(chi, device="cuda")
+    kt = torch.tensor(k.view(np.int32), device="cuda")
+    d = net.sample(tabs, chit, kt).cpu().numpy()
+    dt = sf.sample(tabs, 0, chit, kt).cpu().numpy()
+    out = (chi < np.float32(1e-2)) | (chi > np.float32(1e2))
+    assert out.sum() > 1000 and (~out).sum() > 1000
+    assert np.array_equal(d[out], dt[out]), "outside the trained range the table must sample"
+    # inside: delta = sigmoid(10 y + ln chi) with y the network at the sampler's inputs
+    r = (k.astype(np.float64) + 0.5) * 2.0**-32
+    X = net.features(chi.astype(np.float64), r)
+    y = net.forward(torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
+    z = 10.0 * y + np.log(chi.astype(np.float64))
+    dref = 1.0 / (1.0 + np.exp(-z))
+    e = np.abs(d - dref) / dref
+    assert np.median(e[~out]) < 1e-5 and e[~out].max() < 1e-3
