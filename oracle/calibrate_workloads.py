@@ -6,8 +6,8 @@ workloads, computed once with the FP64 oracle and then frozen.
   dt = 1 / W_rad(chi=1, gamma=1e3).
 * crossed_field_dt: ten mean emission times of the leptons at t = 0,
   dt = 10 / <W_rad>, averaged over the first 2e5 electrons and 2e5 positrons.
-* rotating_e_dt: the step for which the rotating-field cascade of 1e4 seed
-  electrons grows by about 200x in 20 steps (written by calibrate_cascade()).
+* rotating_e_dt: the step for which the rotating-field cascade of 2000 seed
+  electrons grows by about 200x in 20 steps (oracle.cascade.calibrate_rotating_dt).
 
 Run: python -m oracle.calibrate_workloads [--cascade]
 """

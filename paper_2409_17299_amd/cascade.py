@@ -1,0 +1,57 @@
+"""Multi-step cascade on the device: qed_step and qed_merge repeated over
+global steps in a field that is constant within each step (Algorithm 2 per
+step, the new particles merged into the ensemble after it).  The driver only
+moves pointers and counts; every particle operation runs in libsfqed.
+
+The field of step k comes from a caller's function (for the rotating-field
+cascade: the electric field at the antinode of a rotating standing wave,
+Sec. 5.1), and the growth rate of N(t) ~ e^{Gamma t} is the figure of merit
+(Sec. 5.2).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import AppendBuffer, Fields, Store, merge, step, step_cfg
+
+
+def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_capacity, dtype=None, seed: int = 0,
+        cfg=None, on_step=None, stream=None):
+    """species: [(p [n, 3], w [n], tau [n], id [n])] for e-, e+, photons;
+    field_of_step(k): the [1, 6] field (ex ey ez bx by bz) shared by all
+    particles during step k.  Returns (counts [steps + 1, 3], per-step stats,
+    seconds per step, the final device stores)."""
+    import torch
+    dtype = dtype or torch.float32
+    cfg = cfg if cfg is not None else step_cfg(push=True, nev=False)
+    main = [Store.from_arrays(p, w, tau, ids, dtype=dtype, photon=s == 2, capacity=capacity[s])
+            for s, (p, w, tau, ids) in enumerate(species)]
+    for m in main:
+        m.nev = None
+    app = [AppendBuffer(app_capacity[s], dtype) for s in range(3)]
+    counts = [[m.count for m in main]]
+    stats, secs = [], []
+    for k in range(steps):
+        f = Fields.from_array(np.asarray(field_of_step(k), dtype=np.float64).reshape(1, 6), dtype)
+        fields = [f, f, f]
+        t0 = time.perf_counter()
+        rc, st = step(tables, main, fields, app, dt, seed, k, cfg, stream=stream, check=False)
+        if rc != 0:
+            raise RuntimeError(f"cascade step {k}: status {rc}, required capacity {list(st.required_capacity)}")
+        merge(main, fields, app, stream=stream)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+        counts.append([m.count for m in main])
+        stats.append(st)
+        if on_step:
+            on_step(k, counts[-1], st, secs[-1])
+    return np.array(counts, dtype=np.int64), stats, secs, main
+
+
+def growth_rate(counts: np.ndarray, dt: float, first: int = 0) -> float:
+    """Least-squares slope of ln N_total against time over steps >= first."""
+    n = counts.sum(axis=1).astype(np.float64)
+    t = np.arange(n.size) * dt
+    return float(np.polyfit(t[first:], np.log(n[first:]), 1)[0])

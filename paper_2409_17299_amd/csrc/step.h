@@ -5,7 +5,11 @@
 
 namespace sfqed {
 
-constexpr int kStepThreads = 512;   // step kernels: 8 waves per block
+// step kernels: 8 waves per block, two blocks per CU (the emission tables take
+// ~78 KiB of LDS per block).  Measured on the crossed-field step, 640-, 768- and
+// 1024-thread blocks at 5, 6 and 8 waves per SIMD were 3-25% slower: the event
+// loop is not limited by latency hiding.
+constexpr int kStepThreads = 512;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;

@@ -262,3 +262,47 @@ def test_init_tau_parity(env, orc):
     orc.init_tau(o, 77, 5)
     np.testing.assert_allclose(got, o.tau, rtol=4e-16, atol=0)
     assert np.array_equal(got[::3], tau[::3])
+
+
+def test_merge_tight_photon_capacity(env, orc):
+    """Photon capacity below count + appended: the merge counts survivors first,
+    succeeds when they fit exactly and reports a capacity error (changing
+    nothing) when they do not."""
+    torch, sf, tabs = env
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 80_000)] * 2 +
+                             [np.arange(0, 2_000_000, 40_000)])
+    inp = cast_inputs(wl, np.float64)
+    n = sum(d["id"].size for d in inp)
+    cap = [n * 30, n * 30, n * 200]
+    cfg = sf.step_cfg(push=False, gamma_min=2.0)
+    rc, st, gm, gf, ga = run_gpu(sf, torch, tabs, wl, inp, torch.float64, cap, cfg)
+    assert rc == 0 and st.n_pair > 0
+    survivors = int(gm[2].alive[:gm[2].count].sum().item()) + int(
+        (ga[2].records()["alive"] != 0).sum())
+    assert survivors < gm[2].count + ga[2].count
+
+    def stores(photon_cap):
+        out = []
+        for s in range(3):
+            h = gm[s].host()
+            c = gm[s].count + ga[s].count if s < 2 else photon_cap
+            b = sf.Store.from_arrays(h["p"], h["w"], h["tau"], h["id"], dtype=torch.float64, photon=s == 2,
+                                     capacity=max(c, gm[s].count))
+            if s == 2:
+                b.alive[:gm[s].count] = gm[s].alive[:gm[s].count]
+                b.cap = photon_cap
+            out.append(b)
+        return out
+
+    short = stores(survivors - 1)
+    with pytest.raises(sf.SfqedError):
+        sf.merge(short, gf, ga)
+    assert [b.count for b in short] == [gm[s].count for s in range(3)]
+    exact = stores(survivors)
+    sf.merge(exact, gf, ga)
+    assert exact[2].count == survivors
+    roomy = stores(gm[2].count + ga[2].count)
+    sf.merge(roomy, gf, ga)
+    for s in range(3):
+        assert exact[s].count == roomy[s].count
+        assert np.array_equal(exact[s].host()["id"], roomy[s].host()["id"])
