@@ -45,7 +45,8 @@ def kernel_bytes(name: str, st: dict, n_main: list, n_step: int) -> float:
         n = P[0]
         return n * (52 + 4) + (n - main_l) * 8 + (n - ev_l) * 8
     if name == "scan":
-        return P[1] * (4 + 8) + (ev_l + ev_p) * 4
+        # read every count; write index and first-child offset of each particle with events
+        return P[1] * 4 + (ev_l + ev_p) * (4 + 8)
     if name == "write_lepton":
         # per particle with events: state 52 + w 4 (+ root/t_birth) + offset 8 + list 4, final p 12 + tau 8;
         # per child: one 48-byte record

@@ -32,6 +32,7 @@ struct CdfView {
   const float* f32;  // [rows32][cols32]
   int rows32, cols32;
   float s0_32, inv_hs32, x0_32, inv_hx32;
+  float s1_32;       // ln chi of the last FP32 row, s0_32 + (rows32 - 1) / inv_hs32 in FP32
   const double* f64;  // [rows64][cols64]
   int rows64, cols64;
   double s0_64, inv_hs64, x0_64, inv_hx64;
@@ -67,14 +68,21 @@ __device__ __forceinline__ uint4 draw(uint64_t seed, uint64_t id, uint32_t step,
 
 // -ln(u) for u = (k + 1/2) 2^-32 in FP64 (the FP64 path), and in FP32 for the
 // FP32 path (event-time arithmetic is FP32; the optical depth is still
-// accumulated in FP64).  For u > 1/2 the FP32 form uses 1 - u = (~k + 1/2) 2^-32,
-// which is exact, through log1p.
+// accumulated in FP64).  For u > 1/2 the FP32 form works with v = 1 - u =
+// (~k + 1/2) 2^-32, which is exact: -ln(1 - v) = -log1p(-v), evaluated with
+// one logarithm as -ln(w) v / (1 - w) for w = fl(1 - v) (Goldberg, "What every
+// computer scientist should know about floating-point arithmetic", 1991), or v
+// when w rounds to 1.  Both halves take the same single logarithm.
 __device__ __forceinline__ double exp_depth(uint32_t k) {
   return -log(((double)k + 0.5) * 0x1p-32);
 }
 __device__ __forceinline__ float exp_depth32(uint32_t k) {
-  if (k & 0x80000000u) return -log1pf(-((float)(~k) + 0.5f) * 0x1p-32f);
-  return -logf(((float)k + 0.5f) * 0x1p-32f);
+  const bool hi = (k & 0x80000000u) != 0;
+  const float v = ((float)(hi ? ~k : k) + 0.5f) * 0x1p-32f;  // u, or 1 - u
+  const float w = hi ? 1.f - v : v;
+  const float L = logf(w);
+  if (!hi) return -L;
+  return w == 1.f ? v : -L * v * __builtin_amdgcn_rcpf(1.f - w);
 }
 template <typename T>
 __device__ __forceinline__ double exp_depth_t(uint32_t k) {

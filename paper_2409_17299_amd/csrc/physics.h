@@ -109,11 +109,11 @@ __device__ __forceinline__ float herm_g(const float2* h, int n, float t) {
   return h00 * a.x + h10 * a.y + h01 * b.x + h11 * b.y;
 }
 
-// FP32 emission rate; `herm` may point to LDS.
-__device__ __forceinline__ float rate_rad32(const float2* herm, int n, float s0, float inv_h, float chi,
-                                            float gamma) {
+// FP32 emission rate at chi with s = ln chi given; `herm` may point to LDS.
+// The FP32 path divides through the hardware reciprocal (1 ulp).
+__device__ __forceinline__ float rate_rad32_s(const float2* herm, int n, float s0, float inv_h, float chi, float s,
+                                              float gamma) {
   if (!(chi > 0.f)) return 0.f;
-  const float s = logf(chi);
   const float t = (s - s0) * inv_h;
   float g;
   if (t < 0.f) {
@@ -124,15 +124,20 @@ __device__ __forceinline__ float rate_rad32(const float2* herm, int n, float s0,
   } else {
     g = herm_g(herm, n, t);
   }
-  return (float)kAlpha / gamma * chi * expf(g);
+  return (float)kAlpha * chi * expf(g) * __builtin_amdgcn_rcpf(gamma);
+}
+__device__ __forceinline__ float rate_rad32(const float2* herm, int n, float s0, float inv_h, float chi,
+                                            float gamma) {
+  return rate_rad32_s(herm, n, s0, inv_h, chi, chi > 0.f ? logf(chi) : 0.f, gamma);
 }
 
-// FP32 pair rate.  exp(g - 8/(3 chi)) with the large exponent split so that
-// its rounding does not become a relative error of the rate.
-__device__ __forceinline__ float rate_pair32(const float2* herm, int n, float s0, float inv_h, float chi,
-                                             float eps) {
+// FP32 pair rate (s = ln chi given).  exp(g - 8/(3 chi)) with the large
+// exponent split so that its rounding does not become a relative error of the
+// rate; the split is exact for any rounding of the leading quotient, because
+// its residual is taken with an FMA.
+__device__ __forceinline__ float rate_pair32_s(const float2* herm, int n, float s0, float inv_h, float chi, float s,
+                                               float eps) {
   if (!(chi > 0.f)) return 0.f;
-  const float s = logf(chi);
   const float t = (s - s0) * inv_h;
   if (t < 0.f) return 0.f;
   float g;
@@ -144,12 +149,17 @@ __device__ __forceinline__ float rate_pair32(const float2* herm, int n, float s0
   }
   const float c_hi = 2.6666667461395264f;        // 8/3 rounded to FP32
   const float c_lo = -7.947286206899662e-08f;    // 8/3 - c_hi
-  const float qh = c_hi / chi;
-  const float ql = (fmaf(-qh, chi, c_hi) + c_lo) / chi;  // 8/(3 chi) = qh + ql
+  const float rchi = __builtin_amdgcn_rcpf(chi);
+  const float qh = c_hi * rchi;
+  const float ql = (fmaf(-qh, chi, c_hi) + c_lo) * rchi;  // 8/(3 chi) = qh + ql
   const float e = g - qh;
   const float bv = e - g;
   const float err = (g - (e - bv)) + (-qh - bv);          // two-sum error of g - qh
-  return (float)kAlpha / eps * chi * expf(e) * (1.f + (err - ql));
+  return (float)kAlpha * chi * expf(e) * (1.f + (err - ql)) * __builtin_amdgcn_rcpf(eps);
+}
+__device__ __forceinline__ float rate_pair32(const float2* herm, int n, float s0, float inv_h, float chi,
+                                             float eps) {
+  return rate_pair32_s(herm, n, s0, inv_h, chi, chi > 0.f ? logf(chi) : 0.f, eps);
 }
 
 // ---------------------------------------------------------------------------
@@ -208,23 +218,34 @@ __device__ __forceinline__ void log_r64(uint32_t k, double& lr, double& lrc) {
   lr = log((double)k + 0.5) - 32.0 * kLn2;
   lrc = log((double)(~k) + 0.5) - 32.0 * kLn2;
 }
+// logit r = ln((k + 1/2) / (~k + 1/2)) with one logarithm (FP32 path)
+__device__ __forceinline__ float logit_r32(uint32_t k) {
+  return logf(((float)k + 0.5f) * __builtin_amdgcn_rcpf((float)(~k) + 0.5f));
+}
+// sigmoid(z) and sigmoid(-z) from one exponential (FP32 path)
+__device__ __forceinline__ void sigmoid_pair32(float z, float& p, float& q) {
+  const float e = expf(-fabsf(z));
+  const float r = __builtin_amdgcn_rcpf(1.f + e);
+  const float small = e * r;
+  p = z >= 0.f ? r : small;
+  q = z >= 0.f ? small : r;
+}
 
-// Emission: delta and 1 - delta.  `tab` is the FP32 grid (LDS or global).
-__device__ __forceinline__ void sample_rad32(const float* tab, const CdfView& c, float chi, uint32_t k, float& d,
-                                             float& omd) {
-  float lr, lrc;
-  log_r32(k, lr, lrc);
-  const float x = lr - lrc;
+// Emission: delta and 1 - delta at chi (s = ln chi).  `tab` is the FP32 grid
+// (LDS or global).
+__device__ __forceinline__ void sample_rad32_s(const float* tab, const CdfView& c, float chi, float s_chi,
+                                               uint32_t k, float& d, float& omd) {
+  const float x = logit_r32(k);
   float ux = (x - c.x0_32) * c.inv_hx32;
   float extra = 0.f;
   if (ux < 0.f) {
+    const float lr = logf((float)k + 0.5f) - 22.18070977791825f;  // ln r
     const float lr0 = -log1pf(expf(-c.x0_32));
     extra = 3.f * (lr - lr0);
     ux = 0.f;
   }
   ux = fminf(ux, (float)(c.cols32 - 1));
-  const float s_max = c.s0_32 + (float)(c.rows32 - 1) / c.inv_hs32;
-  const float s = fminf(logf(chi), s_max);  // above the grid chi is clamped
+  const float s = fminf(s_chi, c.s1_32);  // above the grid chi is clamped
   const float us = (s - c.s0_32) * c.inv_hs32;
   float q;
   if (us < 0.f) {
@@ -235,9 +256,11 @@ __device__ __forceinline__ void sample_rad32(const float* tab, const CdfView& c,
   } else {
     q = grid_interp<float, float>(tab, c.rows32, c.cols32, us, ux);
   }
-  const float z = q + extra + s;
-  d = 1.f / (1.f + expf(-z));
-  omd = 1.f / (1.f + expf(z));
+  sigmoid_pair32(q + extra + s, d, omd);
+}
+__device__ __forceinline__ void sample_rad32(const float* tab, const CdfView& c, float chi, uint32_t k, float& d,
+                                             float& omd) {
+  sample_rad32_s(tab, c, chi, logf(chi), k, d, omd);
 }
 
 __device__ __forceinline__ void sample_rad64(const CdfView& c, double chi, uint32_t k, double& d, double& omd) {
@@ -269,22 +292,22 @@ __device__ __forceinline__ void sample_rad64(const CdfView& c, double chi, uint3
   omd = 1.0 / (1.0 + exp(z));
 }
 
-// Pairs: xi (electron) and 1 - xi (positron).
-__device__ __forceinline__ void sample_pair32(const float* tab, const CdfView& c, float chi, uint32_t k, float& xi,
-                                              float& omx) {
-  float lr, lrc;
-  log_r32(k, lr, lrc);
-  const float x = lr - lrc;
+// Pairs: xi (electron) and 1 - xi (positron) at chi (s = ln chi).
+__device__ __forceinline__ void sample_pair32_s(const float* tab, const CdfView& c, float s_chi, uint32_t k,
+                                                float& xi, float& omx) {
+  const float x = logit_r32(k);
   const float xa = -fabsf(x);
   float ux = fmaxf((xa - c.x0_32) * c.inv_hx32, 0.f);
   ux = fminf(ux, (float)(c.cols32 - 1));
-  float us = (logf(chi) - c.s0_32) * c.inv_hs32;
+  float us = (s_chi - c.s0_32) * c.inv_hs32;
   us = fminf(fmaxf(us, 0.f), (float)(c.rows32 - 1));
   float q = grid_interp<float, float>(tab, c.rows32, c.cols32, us, ux);
   q = fminf(q, 0.f);
-  const float qq = x > 0.f ? -q : q;
-  xi = 1.f / (1.f + expf(-qq));
-  omx = 1.f / (1.f + expf(qq));
+  sigmoid_pair32(x > 0.f ? -q : q, xi, omx);
+}
+__device__ __forceinline__ void sample_pair32(const float* tab, const CdfView& c, float chi, uint32_t k, float& xi,
+                                              float& omx) {
+  sample_pair32_s(tab, c, logf(chi), k, xi, omx);
 }
 
 __device__ __forceinline__ void sample_pair64(const CdfView& c, double chi, uint32_t k, double& xi, double& omx) {

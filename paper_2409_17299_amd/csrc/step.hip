@@ -221,26 +221,42 @@ struct LdsTables {
 };
 
 template <typename T>
-__device__ __forceinline__ T rate_of(const StepArgs<T>& a, const LdsTables& lt, int process, T chi, T energy) {
+__device__ __forceinline__ T rate_of(const StepArgs<T>& a, const LdsTables& lt, int process, T chi, T s_chi,
+                                     T energy) {
   if constexpr (sizeof(T) == 4) {
     const RateView& r = a.tab.rate[process];
-    return process == 0 ? rate_rad32(lt.herm, r.n, r.hs_lo, r.inv_h, chi, energy)
-                        : rate_pair32(lt.herm, r.n, r.hs_lo, r.inv_h, chi, energy);
+    return process == 0 ? rate_rad32_s(lt.herm, r.n, r.hs_lo, r.inv_h, chi, s_chi, energy)
+                        : rate_pair32_s(lt.herm, r.n, r.hs_lo, r.inv_h, chi, s_chi, energy);
   } else {
     return process == 0 ? rate_rad64(a.tab.rate[0], chi, energy) : rate_pair64(a.tab.rate[1], chi, energy);
   }
 }
 
+// s_chi = ln chi (used by the FP32 path only)
 template <typename T>
-__device__ __forceinline__ void sample_of(const StepArgs<T>& a, const LdsTables& lt, int process, T chi, uint32_t k,
-                                          T& v, T& omv) {
+__device__ __forceinline__ void sample_of(const StepArgs<T>& a, const LdsTables& lt, int process, T chi, T s_chi,
+                                          uint32_t k, T& v, T& omv) {
   if constexpr (sizeof(T) == 4) {
-    if (process == 0) sample_rad32(lt.cdf, a.tab.cdf[0], chi, k, v, omv);
-    else sample_pair32(lt.cdf, a.tab.cdf[1], chi, k, v, omv);
+    if (process == 0) sample_rad32_s(lt.cdf, a.tab.cdf[0], chi, s_chi, k, v, omv);
+    else sample_pair32_s(lt.cdf, a.tab.cdf[1], s_chi, k, v, omv);
   } else {
     if (process == 0) sample_rad64(a.tab.cdf[0], chi, k, v, omv);
     else sample_pair64(a.tab.cdf[1], chi, k, v, omv);
   }
+}
+
+// ln chi for the FP32 path (the FP64 path takes its logarithms inside)
+template <typename T>
+__device__ __forceinline__ T log_chi(T chi) {
+  if constexpr (sizeof(T) == 4) return chi > 0.f ? logf(chi) : 0.f;
+  else return T(0);
+}
+
+// a / b: the hardware reciprocal on the FP32 path, IEEE division on the FP64 path
+template <typename T>
+__device__ __forceinline__ T quot(T a, T b) {
+  if constexpr (sizeof(T) == 4) return a * __builtin_amdgcn_rcpf(b);
+  else return a / b;
 }
 
 template <typename T>
@@ -288,7 +304,8 @@ __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTable
   const T g = sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
   T W = T(0);
   const T chi0 = chi_of<T>(L.p, g, L.E, L.B);
-  if (a.emission && !L.capped && (double)g >= a.gamma_min) W = rate_of<T>(a, lt, 0, chi0, g);
+  const T s0 = log_chi<T>(chi0);
+  if (a.emission && !L.capped && (double)g >= a.gamma_min) W = rate_of<T>(a, lt, 0, chi0, s0, g);
   const T rem = dtT - L.t;
   const double X = (double)W * (double)rem;
   if (!(W > T(0)) || L.tau > X) {  // no event before the end of the step
@@ -298,18 +315,19 @@ __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTable
     L.changed |= X > 0.0 || a.push || a.positions;
     return true;
   }
-  T h = (T)L.tau / W;  // the optical depth runs out after h
+  T h = quot<T>((T)L.tau, W);  // the optical depth runs out after h
   if (h > rem) h = rem;
   advance_lepton<T>(a, L, q, h);
   L.t += h;
   const uint4 u = draw(a.seed, L.id, a.step, (uint32_t)L.j);
-  T chi_e = chi0;  // the particle as it is at the event (unchanged unless pushed)
+  T chi_e = chi0, s_e = s0;  // the particle as it is at the event (unchanged unless pushed)
   if (a.push) {
     const T g2 = sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
     chi_e = chi_of<T>(L.p, g2, L.E, L.B);
+    s_e = log_chi<T>(chi_e);
   }
   T d, omd;
-  sample_of<T>(a, lt, 0, chi_e, u.x, d, omd);
+  sample_of<T>(a, lt, 0, chi_e, s_e, u.x, d, omd);
   if (kWrite) {
     const int64_t o = out_base + L.j;
     if (o < a.out_cap) {
@@ -338,7 +356,9 @@ __device__ __forceinline__ bool photon_iter(const StepArgs<T>& a, const LdsTable
   if (!(L.t < dtT)) return true;
   const T eps = sqrt(L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
   T W = T(0);
-  if (a.pair && eps >= T(2)) W = rate_of<T>(a, lt, 1, chi_of<T>(L.p, eps, L.E, L.B), eps);
+  const T chi0 = chi_of<T>(L.p, eps, L.E, L.B);
+  const T s0 = log_chi<T>(chi0);
+  if (a.pair && eps >= T(2)) W = rate_of<T>(a, lt, 1, chi0, s0, eps);
   const T rem = dtT - L.t;
   const double X = (double)W * (double)rem;
   const T inv_eps = eps > T(0) ? T(1) / eps : T(0);
@@ -353,7 +373,7 @@ __device__ __forceinline__ bool photon_iter(const StepArgs<T>& a, const LdsTable
     L.changed |= X > 0.0 || a.positions;
     return true;
   }
-  T h = (T)L.tau / W;
+  T h = quot<T>((T)L.tau, W);
   if (h > rem) h = rem;
   if (a.positions) {
     L.x[0] += L.p[0] * inv_eps * h;
@@ -363,9 +383,8 @@ __device__ __forceinline__ bool photon_iter(const StepArgs<T>& a, const LdsTable
   L.t += h;
   if (kWrite) {
     const uint4 u = draw(a.seed, L.id, a.step, 0u);
-    const T chi = chi_of<T>(L.p, eps, L.E, L.B);
     T xi, omx;
-    sample_of<T>(a, lt, 1, chi, u.x, xi, omx);
+    sample_of<T>(a, lt, 1, chi0, s0, u.x, xi, omx);
     const int64_t o = out_base;
     if (o < a.out_cap) {
       const uint4 v = draw(a.seed, L.id, a.step, 0x80000000u);
@@ -602,9 +621,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t k = k0 + i;
-    if (k < s.n) {
-      s.offsets[k] = oc;
-      if (c[i] > 0) s.list[of++] = (int32_t)k;
+    if (k < s.n && c[i] > 0) {  // event particles: index and first child offset, in order
+      s.list[of] = (int32_t)k;
+      s.offsets[of] = oc;
+      ++of;
     }
     oc += c[i];
   }
@@ -628,7 +648,7 @@ __global__ void __launch_bounds__(kStepThreads) k_write_lepton(StepArgs<T> a) {
     if (!have && e < n) {
       const int64_t k = a.list[e];
       load_lane<T>(a, k, L);
-      obase = a.offsets[k];
+      obase = a.offsets[e];
       have = true;
     }
     if (!__any(have)) break;
@@ -648,7 +668,7 @@ __global__ void __launch_bounds__(kStepThreads) k_write_photon(StepArgs<T> a) {
     const int64_t k = a.list[e];
     Lane<T> L;
     load_lane<T>(a, k, L);
-    photon_iter<T, true>(a, lt, L, a.offsets[k]);
+    photon_iter<T, true>(a, lt, L, a.offsets[e]);
     store_final<T>(a, L, false, true);  // the photon is removed at its event
   }
 }

@@ -449,6 +449,7 @@ qed_status build_tables(const qed_table_cfg& cfg, hipStream_t stream, qed_tables
     cv.inv_hs32 = (float)(1.0 / hs32);
     cv.x0_32 = (float)g.x0[p];
     cv.inv_hx32 = (float)(1.0 / hx32);
+    cv.s1_32 = cv.s0_32 + (float)(cv.rows32 - 1) / cv.inv_hs32;
     cv.f64 = c64;
     cv.rows64 = g.rows64[p];
     cv.cols64 = g.cols64[p];
