@@ -223,9 +223,11 @@ struct EventLog {
 // store.
 template <typename T>
 qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const qed_step_cfg* cfg,
-                      const qed_ensemble* ens, qed_append* app, int species, bool from_main, int64_t begin,
-                      int64_t n, double dt, uint64_t seed, uint32_t step, int* slot, bool positions, EventLog& log,
-                      qed_step_stats* stats) {
+                      const qed_ensemble* ens, qed_append* app, int species, bool from_main, int64_t begin0,
+                      int64_t n0, int64_t begin1, int64_t n1, double dt, uint64_t seed, uint32_t step, int* slot,
+                      bool positions, EventLog& log, qed_step_stats* stats) {
+  // part 0: species, particles [begin0, begin0 + n0); part 1 (leptons): species + 1, [begin1, begin1 + n1)
+  const int64_t n = n0 + n1;
   if (n <= 0) return QED_OK;
   qed_status rc = ensure_scratch(S, n);
   if (rc != QED_OK) return rc;
@@ -236,15 +238,20 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   const bool photon = species == 2;
   StepArgs<T> a;
   std::memset(&a, 0, sizeof(a));
-  if (from_main) {
-    a.src = view_of<T>(ens->s[species]);
-  } else {
-    a.src_rec = static_cast<Rec<T>*>(app[species].rec);
-    a.src_pos = static_cast<T*>(app[species].pos);
+  const int parts = n1 > 0 ? 2 : 1;
+  for (int q = 0; q < parts; ++q) {
+    if (from_main) {
+      a.src[q] = view_of<T>(ens->s[species + q]);
+    } else {
+      a.src_rec[q] = static_cast<Rec<T>*>(app[species + q].rec);
+      a.src_pos[q] = static_cast<T*>(app[species + q].pos);
+    }
   }
+  a.begin[0] = begin0;
+  a.begin[1] = begin1;
   a.species = species;
   a.from_main = from_main ? 1 : 0;
-  a.begin = begin;
+  a.n0 = n0;
   a.n = n;
   for (int k = 0; k < 3; ++k) a.f[k] = fields_of<T>(ens->f[k]);
   int64_t* cursor;
@@ -361,22 +368,24 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   log.st = st;
   qed_status rc;
   int64_t launches = 0;
-  auto launch = [&](int species, bool from_main, int64_t begin, int64_t n) -> qed_status {
-    if (n <= 0) return QED_OK;
+  // one launch per round for the leptons (electrons, then positrons) and per
+  // range of photons
+  auto launch = [&](int species, bool from_main, int64_t begin0, int64_t n0, int64_t begin1,
+                    int64_t n1) -> qed_status {
+    if (n0 + n1 <= 0) return QED_OK;
     ++launches;
-    return run_launch<T>(S, st, tab, cfg, ens, app, species, from_main, begin, n, dt, seed, step, &slot, positions,
-                         log, &local);
+    return run_launch<T>(S, st, tab, cfg, ens, app, species, from_main, begin0, n0, begin1, n1, dt, seed, step,
+                         &slot, positions, log, &local);
   };
   // round 0: the input ensemble, then the photons its leptons emitted
-  if ((rc = launch(0, true, 0, ens->s[0].count)) != QED_OK) return rc;
-  if ((rc = launch(1, true, 0, ens->s[1].count)) != QED_OK) return rc;
+  if ((rc = launch(0, true, 0, ens->s[0].count, 0, ens->s[1].count)) != QED_OK) return rc;
   if ((rc = read_cursors()) != QED_OK) return rc;
   int64_t g_done = 0;
   bool overflow = cur[0] > capg;
   if (!overflow) {
-    if ((rc = launch(2, true, 0, ens->s[2].count)) != QED_OK) return rc;
+    if ((rc = launch(2, true, 0, ens->s[2].count, 0, 0)) != QED_OK) return rc;
     const int64_t g_hi = cur[0];
-    if ((rc = launch(2, false, 0, g_hi)) != QED_OK) return rc;
+    if ((rc = launch(2, false, 0, g_hi, 0, 0)) != QED_OK) return rc;
     g_done = g_hi;
     if ((rc = read_cursors()) != QED_OK) return rc;
     overflow = cur[0] > capg || cur[1] > capl;
@@ -384,8 +393,7 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   int64_t rounds = 1, l_done = 0;
   while (!overflow && cur[1] > l_done) {
     const int64_t l_hi = cur[1];
-    if ((rc = launch(0, false, l_done, l_hi - l_done)) != QED_OK) return rc;
-    if ((rc = launch(1, false, l_done, l_hi - l_done)) != QED_OK) return rc;
+    if ((rc = launch(0, false, l_done, l_hi - l_done, l_done, l_hi - l_done)) != QED_OK) return rc;
     l_done = l_hi;
     if ((rc = read_cursors()) != QED_OK) return rc;
     if (cur[0] > capg) {
@@ -393,7 +401,7 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
       break;
     }
     const int64_t g_hi = cur[0];
-    if ((rc = launch(2, false, g_done, g_hi - g_done)) != QED_OK) return rc;
+    if ((rc = launch(2, false, g_done, g_hi - g_done, 0, 0)) != QED_OK) return rc;
     g_done = g_hi;
     if ((rc = read_cursors()) != QED_OK) return rc;
     overflow = cur[0] > capg || cur[1] > capl;

@@ -22,14 +22,20 @@ constexpr int kStatMaxEvents = 0;
 constexpr int kStatCapped = 1;
 constexpr int kStatEventParticles = 2;  // + 0 leptons, + 1 photons
 
+// A launch covers up to two source ranges ("parts"): electrons and positrons
+// go together (part 0 e-, part 1 e+), photons alone (part 0).  Particle k of
+// the launch is particle begin[0] + k of part 0 for k < n0, else particle
+// begin[1] + k - n0 of part 1, so the append order is that of separate
+// launches for the two species, one after the other.
 template <typename T>
 struct StepArgs {
-  SpeciesView<T> src;  // the input ensemble (from_main)
-  Rec<T>* src_rec;     // or appended records
-  T* src_pos;          // their positions (4 per record) or null
-  int32_t species;     // species of the source (0 e-, 1 e+, 2 photon)
-  int32_t from_main;   // 1: source is the input ensemble (root = species << 30 | index)
-  int64_t begin, n;    // particles [begin, begin + n) of the source
+  SpeciesView<T> src[2];  // the input ensemble of each part (from_main)
+  Rec<T>* src_rec[2];     // or its appended records
+  T* src_pos[2];          // their positions (4 per record) or null
+  int64_t begin[2];       // first particle of each part in its source
+  int32_t species;        // species of part 0 (0 e-, 2 photon); part 1 is species + 1
+  int32_t from_main;      // 1: sources are the input ensemble (root = species << 30 | index)
+  int64_t n0, n;          // particles of part 0; of the launch
   FieldView<T> f[3];
   Rec<T>* out_rec[2];  // leptons: out[0] photons; photons: out[0] e-, out[1] e+
   T* out_pos[2];

@@ -92,7 +92,9 @@ __device__ int64_t lookback(uint64_t* st, int64_t tile, int64_t agg, int64_t bas
 // ------------------------------------------------------------------ particle state
 template <typename T>
 struct Lane {
-  int64_t k;
+  int64_t k;  // particle of the launch
+  int64_t i;  // its index in the source of its part
+  int32_t part;
   T p[3], x[3], E[3], B[3];
   double tau;
   T t, t0;
@@ -106,10 +108,13 @@ struct Lane {
 
 template <typename T>
 __device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<T>& L) {
-  const int64_t i = a.begin + k;
+  const int part = k >= a.n0 ? 1 : 0;
+  const int64_t i = a.begin[part] + (part ? k - a.n0 : k);
   L.k = k;
+  L.i = i;
+  L.part = part;
   if (a.from_main) {
-    const SpeciesView<T>& s = a.src;
+    const SpeciesView<T>& s = a.src[part];
     L.p[0] = s.px[i];
     L.p[1] = s.py[i];
     L.p[2] = s.pz[i];
@@ -123,12 +128,12 @@ __device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<
     L.tau = s.tau[i];
     L.id = s.id[i];
     L.w = s.w[i];
-    L.root = ((uint32_t)a.species << 30) | (uint32_t)i;
+    L.root = ((uint32_t)(a.species + part) << 30) | (uint32_t)i;
     L.t = T(0);
     L.t0 = T(0);
   } else {
     Rec<T> r;
-    rec_load<T>(a.src_rec, i, r);
+    rec_load<T>(a.src_rec[part], i, r);
     L.p[0] = r.px;
     L.p[1] = r.py;
     L.p[2] = r.pz;
@@ -139,7 +144,7 @@ __device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<
     L.w = r.w;
     L.root = r.root;
     if (a.positions) {
-      const T* q = a.src_pos + 4 * i;
+      const T* q = a.src_pos[part] + 4 * i;
       L.x[0] = q[0];
       L.x[1] = q[1];
       L.x[2] = q[2];
@@ -175,10 +180,10 @@ __device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<
 // optical depth; for records also the event count and alive flag when asked.
 template <typename T>
 __device__ __forceinline__ void store_final(const StepArgs<T>& a, const Lane<T>& L, bool momentum, bool died) {
-  const int64_t i = a.begin + L.k;
+  const int64_t i = L.i;
   if (!L.changed && !died && !(a.write_nev && !a.from_main)) return;  // W = 0 all along: nothing moved
   if (a.from_main) {
-    const SpeciesView<T>& s = a.src;
+    const SpeciesView<T>& s = a.src[L.part];
     if (momentum) {
       s.px[i] = L.p[0];
       s.py[i] = L.p[1];
@@ -205,9 +210,9 @@ __device__ __forceinline__ void store_final(const StepArgs<T>& a, const Lane<T>&
   r.root = L.root;
   r.nev = L.j;
   r.alive = died ? 0u : 1u;
-  rec_store_part<T>(a.src_rec, i, r, momentum ? 0 : C::kTau, (a.write_nev || died) ? C::kCount : C::kTail);
+  rec_store_part<T>(a.src_rec[L.part], i, r, momentum ? 0 : C::kTau, (a.write_nev || died) ? C::kCount : C::kTail);
   if (a.positions) {
-    T* q = a.src_pos + 4 * i;
+    T* q = a.src_pos[L.part] + 4 * i;
     q[0] = L.x[0];
     q[1] = L.x[1];
     q[2] = L.x[2];
@@ -486,11 +491,11 @@ __global__ void __launch_bounds__(kStepThreads) k_count_lepton(StepArgs<T> a) {
   extern __shared__ float lds[];
   const LdsTables lt = stage_tables<T, false>(a, lds);
   const uint64_t n = (uint64_t)a.n;
-  const T q = a.species == 0 ? T(-1) : T(1);
   const uint32_t waves = gridDim.x * (kStepThreads / 64);
   WaveQueue wq;
   wq_init(wq);
   Lane<T> L;
+  T q = T(-1);  // charge of the lane's particle
   bool have = false;
   int32_t local_max = 0;
   bool capped = false;
@@ -498,13 +503,13 @@ __global__ void __launch_bounds__(kStepThreads) k_count_lepton(StepArgs<T> a) {
     const uint64_t k = wq_take(wq, !have, n, &a.queue[0], waves);
     if (!have && k < n) {
       load_lane<T>(a, (int64_t)k, L);
+      q = a.species + L.part == 0 ? T(-1) : T(1);
       have = true;
     }
     if (!__any(have)) break;
     if (have && lepton_iter<T, false>(a, lt, L, q, 0)) {
-      const int64_t i = a.begin + L.k;
       a.counts[L.k] = L.j;
-      if (a.from_main && a.src.nev) a.src.nev[i] = L.j;
+      if (a.from_main && a.src[L.part].nev) a.src[L.part].nev[L.i] = L.j;
       if (L.j == 0) store_final<T>(a, L, a.push != 0, false);
       local_max = L.j > local_max ? L.j : local_max;
       capped |= L.capped;
@@ -529,14 +534,13 @@ __global__ void __launch_bounds__(kStepThreads) k_count_photon(StepArgs<T> a) {
        k += (int64_t)gridDim.x * kStepThreads) {
     Lane<T> L;
     load_lane<T>(a, k, L);
-    const int64_t i = a.begin + k;
-    if (a.from_main && a.src.alive[i] == 0) {  // a photon removed earlier is not processed
+    if (a.from_main && a.src[0].alive[L.i] == 0) {  // a photon removed earlier is not processed
       a.counts[k] = 0;
       continue;
     }
     photon_iter<T, false>(a, lt, L, 0);
     a.counts[k] = L.j;
-    if (a.from_main && a.src.nev) a.src.nev[i] = L.j;
+    if (a.from_main && a.src[0].nev) a.src[0].nev[L.i] = L.j;
     if (L.j == 0) store_final<T>(a, L, false, false);
     any_event |= L.j;
   }
@@ -636,11 +640,11 @@ __global__ void __launch_bounds__(kStepThreads) k_write_lepton(StepArgs<T> a) {
   extern __shared__ float lds[];
   const LdsTables lt = stage_tables<T, false>(a, lds);
   const uint64_t n = (uint64_t)*a.list_len;
-  const T q = a.species == 0 ? T(-1) : T(1);
   const uint32_t waves = gridDim.x * (kStepThreads / 64);
   WaveQueue wq;
   wq_init(wq);
   Lane<T> L;
+  T q = T(-1);  // charge of the lane's particle
   int64_t obase = 0;
   bool have = false;
   while (true) {
@@ -648,6 +652,7 @@ __global__ void __launch_bounds__(kStepThreads) k_write_lepton(StepArgs<T> a) {
     if (!have && e < n) {
       const int64_t k = a.list[e];
       load_lane<T>(a, k, L);
+      q = a.species + L.part == 0 ? T(-1) : T(1);
       obase = a.offsets[e];
       have = true;
     }
