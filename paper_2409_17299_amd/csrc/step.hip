@@ -1,8 +1,9 @@
 // step.hip -- the event-generator step on the GPU.
 //
-// One launch processes a contiguous range of one species (Algorithm 1 for
-// every particle of the range; Algorithm 2 is the host loop over rounds in
-// api.cpp).  A launch is three kernels:
+// One launch processes the leptons of one generation round (electrons, then
+// positrons, as two source ranges) or a range of photons: Algorithm 1 for
+// every particle; Algorithm 2 is the host loop over rounds in api.cpp.  A
+// launch is three kernels:
 //   count: every lane runs the sub-cycle loop of one particle, one sub-cycle
 //          per loop trip; a lane whose particle reached the end of the step
 //          takes the next one from a global queue (one atomic per wave), so
