@@ -296,7 +296,7 @@ def precision_sweep(sf, torch, n_total: int, chunk: int) -> dict:
                                         "max_rel_err": mx, "mean_rel_err": sm / half}
         out[name] = res
     return {"workload": "static_b_sweep", "particles": n_total, "chi_range": [1e-3, 1e3], "dt": wl.dt,
-            "seconds": time.perf_counter() - t0, "judge": "fp64 GPU path (oracle-checked on a 1/1000 subsample)",
+            "seconds": time.perf_counter() - t0, "reference": "fp64 GPU path (oracle-checked on a 1/1000 subsample)",
             **out}
 
 
@@ -320,7 +320,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU: the event generator runs on a single MI355X here "
-              "(a multi-GPU run would shard particles by index; see DESIGN.md)", file=sys.stderr)
+              "(a multi-GPU run would shard the particles by index and replicate the tables)", file=sys.stderr)
         return 2
 
     import numpy as np
