@@ -22,7 +22,8 @@ void set_error(const std::string& msg) { g_error = msg; }
 
 namespace {
 
-constexpr int kSlots = 3072;           // zeroed work counters per step
+constexpr int kSlots = 16384;          // zeroed work counters per step
+constexpr int kLaunchWords = 2 * kQueueWords + kQueueStride;  // per launch: two queues, the scan ticket
 constexpr int kCtrlWords = kSlots + 64;
 constexpr int kCurPhoton = kSlots + 0;  // append count of photons
 constexpr int kCurLepton = kSlots + 1;  // append count of electrons (= positrons)
@@ -231,7 +232,7 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   if (n <= 0) return QED_OK;
   qed_status rc = ensure_scratch(S, n);
   if (rc != QED_OK) return rc;
-  if (*slot + 3 > kSlots) {
+  if (*slot + kLaunchWords > kSlots) {
     SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t) * kSlots, st));
     *slot = 0;
   }
@@ -305,10 +306,10 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   s.state_c = S->state_c;
   s.state_f = S->state_f;
   s.epoch = next_epoch(S);
-  s.ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot + 2);
+  s.ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot + 2 * kQueueWords);
   s.num_tiles = (n + kScanTile - 1) / kScanTile;
   s.event_particles = reinterpret_cast<unsigned long long*>(S->ctrl + kStats + kStatEventParticles + p);
-  *slot += 3;
+  *slot += kLaunchWords;
 
   const int k_count = photon ? 3 : 0, k_write = photon ? 4 : 2;
   hipEvent_t e0 = log.begin();

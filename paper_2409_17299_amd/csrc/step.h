@@ -6,10 +6,16 @@
 namespace sfqed {
 
 // step kernels: 8 waves per block, two blocks per CU (the emission tables take
-// ~78 KiB of LDS per block).  Measured on the crossed-field step, 640-, 768- and
-// 1024-thread blocks at 5, 6 and 8 waves per SIMD were 3-25% slower: the event
-// loop is not limited by latency hiding.
+// ~78 KiB of LDS per block), so four waves per SIMD; the FP32 lepton kernels
+// are held to the register budget of that occupancy (the FP64 ones keep their
+// tables in HBM and are limited by registers instead).
 constexpr int kStepThreads = 512;
+constexpr int kStepWavesPerSimd = 4;
+// lepton work queue: counters per launch and kernel (see wq_take)
+constexpr int kQueueParts = 8;
+constexpr int kQueueStride = 16;  // 64-bit words between counters: one 128-byte line each
+constexpr int kQueueWords = kQueueParts * kQueueStride;
+constexpr uint64_t kChunkMin = 256, kChunkMax = 8192;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
@@ -44,7 +50,7 @@ struct StepArgs {
   int64_t* offsets;    // [n]
   int32_t* list;       // [n]
   const int64_t* list_len;
-  unsigned long long* queue;  // [2] work counters of the count and write kernels (zero at launch)
+  unsigned long long* queue;  // work counters of the count, then the write kernel: 2 x kQueueWords, zero at launch
   unsigned long long* stats;
   double dt;
   uint64_t seed;

@@ -90,6 +90,38 @@ __device__ int64_t lookback(uint64_t* st, int64_t tile, int64_t agg, int64_t bas
   return excl;
 }
 
+// ------------------------------------------------------------------ per-lane choice of launch constants
+// A launch may cover two source ranges, so a lane picks its arrays at run time.
+// Indexing an array of kernel arguments with a per-lane index makes the
+// compiler fetch the element with a vector load from argument memory, which
+// puts a memory round trip in front of every access through the pointer.  The
+// empty asm statements keep each candidate a uniform scalar-register value, so
+// that the choice is a register select.  Pointers pass through the global
+// address space, so that accesses through the result stay global (not flat)
+// memory instructions.
+template <typename V>
+__device__ __forceinline__ V pin_sgpr(V v) {
+  asm("" : "+s"(v));
+  return v;
+}
+template <typename E>
+__device__ __forceinline__ __attribute__((address_space(1))) E* pin_sgpr(E* p) {
+  using G = __attribute__((address_space(1))) E*;
+  G g = (G)p;
+  asm("" : "+s"(g));
+  return g;
+}
+template <typename V>
+__device__ __forceinline__ auto pick(bool second, V a, V b) {
+  const auto x = pin_sgpr(a), y = pin_sgpr(b);
+  return (V)(second ? y : x);
+}
+template <typename V>
+__device__ __forceinline__ auto pick3(uint32_t which, V a, V b, V c) {
+  const auto x = pin_sgpr(a), y = pin_sgpr(b), z = pin_sgpr(c);
+  return (V)(which == 0 ? x : (which == 1 ? y : z));
+}
+
 // ------------------------------------------------------------------ particle state
 template <typename T>
 struct Lane {
@@ -107,34 +139,60 @@ struct Lane {
   bool changed;  // state differs from what was loaded
 };
 
+// E and B of the particle's root (children keep the fields of the particle
+// they descend from; the fields are constant over the step)
 template <typename T>
-__device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<T>& L) {
-  const int part = k >= a.n0 ? 1 : 0;
-  const int64_t i = a.begin[part] + (part ? k - a.n0 : k);
+__device__ __forceinline__ void load_fields(const StepArgs<T>& a, uint32_t root, T E[3], T B[3]) {
+  const uint32_t sp = root >> 30;
+  const int64_t idx = (int64_t)(root & 0x3FFFFFFFu);
+  const FieldView<T>& f0 = a.f[0];
+  const FieldView<T>& f1 = a.f[1];
+  const FieldView<T>& f2 = a.f[2];
+  const int64_t o = pick3(sp, f0.stride, f1.stride, f2.stride) ? idx : 0;
+  E[0] = pick3(sp, f0.ex, f1.ex, f2.ex)[o];
+  E[1] = pick3(sp, f0.ey, f1.ey, f2.ey)[o];
+  E[2] = pick3(sp, f0.ez, f1.ez, f2.ez)[o];
+  B[0] = pick3(sp, f0.bx, f1.bx, f2.bx)[o];
+  B[1] = pick3(sp, f0.by, f1.by, f2.by)[o];
+  B[2] = pick3(sp, f0.bz, f1.bz, f2.bz)[o];
+}
+
+// Issues the loads of the state of particle k of the launch; a particle of the
+// input ensemble (kMain) also loads its fields, an appended particle finds them
+// through its root afterwards.  Positions load only when they are tracked.
+template <typename T, bool kMain>
+__device__ __forceinline__ void load_state(const StepArgs<T>& a, int64_t k, Lane<T>& L) {
+  const bool p1 = k >= a.n0;
+  const int part = p1 ? 1 : 0;
+  const int64_t i = pick(p1, a.begin[0], a.begin[1]) + (p1 ? k - a.n0 : k);
   L.k = k;
   L.i = i;
   L.part = part;
-  if (a.from_main) {
-    const SpeciesView<T>& s = a.src[part];
-    L.p[0] = s.px[i];
-    L.p[1] = s.py[i];
-    L.p[2] = s.pz[i];
-    if (a.positions) {
-      L.x[0] = s.x[i];
-      L.x[1] = s.y[i];
-      L.x[2] = s.z[i];
-    } else {
-      L.x[0] = L.x[1] = L.x[2] = T(0);
-    }
-    L.tau = s.tau[i];
-    L.id = s.id[i];
-    L.w = s.w[i];
+  L.j = 0;
+  L.capped = false;
+  L.changed = false;
+  if constexpr (kMain) {
+    // the root is the particle itself: its fields load together with its state
     L.root = ((uint32_t)(a.species + part) << 30) | (uint32_t)i;
+    load_fields<T>(a, L.root, L.E, L.B);
+    const SpeciesView<T>& s0 = a.src[0];
+    const SpeciesView<T>& s1 = a.src[1];
+    L.p[0] = pick(p1, s0.px, s1.px)[i];
+    L.p[1] = pick(p1, s0.py, s1.py)[i];
+    L.p[2] = pick(p1, s0.pz, s1.pz)[i];
+    if (a.positions) {
+      L.x[0] = pick(p1, s0.x, s1.x)[i];
+      L.x[1] = pick(p1, s0.y, s1.y)[i];
+      L.x[2] = pick(p1, s0.z, s1.z)[i];
+    }
+    L.tau = pick(p1, s0.tau, s1.tau)[i];
+    L.id = pick(p1, s0.id, s1.id)[i];
+    L.w = pick(p1, s0.w, s1.w)[i];
     L.t = T(0);
     L.t0 = T(0);
   } else {
     Rec<T> r;
-    rec_load<T>(a.src_rec[part], i, r);
+    rec_load<T>(pick(p1, a.src_rec[0], a.src_rec[1]), i, r);
     L.p[0] = r.px;
     L.p[1] = r.py;
     L.p[2] = r.pz;
@@ -145,79 +203,131 @@ __device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<
     L.w = r.w;
     L.root = r.root;
     if (a.positions) {
-      const T* q = a.src_pos[part] + 4 * i;
+      const T* q = pick(p1, a.src_pos[0], a.src_pos[1]) + 4 * i;
       L.x[0] = q[0];
       L.x[1] = q[1];
       L.x[2] = q[2];
-    } else {
-      L.x[0] = L.x[1] = L.x[2] = T(0);
     }
   }
-  const uint32_t sp = L.root >> 30;
-  const int64_t idx = (int64_t)(L.root & 0x3FFFFFFFu);
-  const FieldView<T>& f0 = a.f[0];
-  const FieldView<T>& f1 = a.f[1];
-  const FieldView<T>& f2 = a.f[2];
-  const T* ex = sp == 0 ? f0.ex : (sp == 1 ? f1.ex : f2.ex);
-  const T* ey = sp == 0 ? f0.ey : (sp == 1 ? f1.ey : f2.ey);
-  const T* ez = sp == 0 ? f0.ez : (sp == 1 ? f1.ez : f2.ez);
-  const T* bx = sp == 0 ? f0.bx : (sp == 1 ? f1.bx : f2.bx);
-  const T* by = sp == 0 ? f0.by : (sp == 1 ? f1.by : f2.by);
-  const T* bz = sp == 0 ? f0.bz : (sp == 1 ? f1.bz : f2.bz);
-  const int64_t st = sp == 0 ? f0.stride : (sp == 1 ? f1.stride : f2.stride);
-  const int64_t o = st ? idx : 0;
-  L.E[0] = ex[o];
-  L.E[1] = ey[o];
-  L.E[2] = ez[o];
-  L.B[0] = bx[o];
-  L.B[1] = by[o];
-  L.B[2] = bz[o];
-  L.j = 0;
-  L.capped = false;
-  L.changed = false;
 }
 
-// Final state of a processed particle: momentum (when it changed), position,
-// optical depth; for records also the event count and alive flag when asked.
+template <typename T>
+__device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<T>& L) {
+  L.x[0] = L.x[1] = L.x[2] = T(0);
+  if (a.from_main) {
+    load_state<T, true>(a, k, L);
+  } else {
+    load_state<T, false>(a, k, L);
+    load_fields<T>(a, L.root, L.E, L.B);
+  }
+}
+
+// What a lane stores: a child record, or its particle's final state (momentum
+// when it changed, position, optical depth; for records also the event count
+// and alive flag when asked) and, in the count kernel, the event count.  The
+// lepton kernels keep it over to the start of the next loop trip (see the
+// pipeline below); the photon kernels store it at once.
+constexpr uint32_t kOutChild = 1u;     // r is a child record for the append buffer, at = its index
+constexpr uint32_t kOutFinal = 2u;     // r holds the final state of particle `at` of its source
+constexpr uint32_t kOutCount = 4u;     // the event count r.nev goes to counts[k] (and nev[at] of the source)
+constexpr uint32_t kOutMomentum = 8u;  // the final state includes the momentum
+constexpr uint32_t kOutDied = 16u;     // the particle was removed (photon at its event)
+constexpr uint32_t kOutPart1 = 32u;    // the particle belongs to the second source range
+
+template <typename T>
+struct Outbox {
+  Rec<T> r;
+  T x[3];
+  int64_t at;
+  int64_t k;
+  uint32_t what;
+};
+
+template <typename T>
+__device__ __forceinline__ void stage_final(const StepArgs<T>& a, const Lane<T>& L, bool momentum, bool died,
+                                            bool final_state, Outbox<T>& O) {
+  O.r.px = L.p[0];
+  O.r.py = L.p[1];
+  O.r.pz = L.p[2];
+  O.r.tb = L.t0;
+  O.r.tau = L.tau;
+  O.r.id = L.id;
+  O.r.w = L.w;
+  O.r.root = L.root;
+  O.r.nev = L.j;
+  O.r.alive = died ? 0u : 1u;
+  O.x[0] = L.x[0];
+  O.x[1] = L.x[1];
+  O.x[2] = L.x[2];
+  O.at = L.i;
+  O.k = L.k;
+  // W = 0 all along: nothing moved, nothing to store
+  const bool store = final_state && (L.changed || died || (a.write_nev && !a.from_main));
+  O.what |= (store ? kOutFinal : 0u) | (momentum ? kOutMomentum : 0u) | (died ? kOutDied : 0u) |
+            (L.part ? kOutPart1 : 0u);
+}
+
+template <typename T>
+__device__ __forceinline__ void flush(const StepArgs<T>& a, Outbox<T>& O) {
+  const uint32_t what = O.what;
+  const bool p1 = (what & kOutPart1) != 0;
+  const int64_t i = O.at;
+  if (what & kOutChild) {
+    rec_store<T>(a.out_rec[0], i, O.r);
+    if (a.positions) {
+      T* q = a.out_pos[0] + 4 * i;
+      q[0] = O.x[0];
+      q[1] = O.x[1];
+      q[2] = O.x[2];
+      q[3] = T(0);
+    }
+  }
+  if (what & kOutCount) {
+    a.counts[O.k] = O.r.nev;
+    if (a.from_main) {
+      int32_t* nev = pick(p1, a.src[0].nev, a.src[1].nev);
+      if (nev) nev[i] = O.r.nev;
+    }
+  }
+  if (what & kOutFinal) {
+    const bool momentum = (what & kOutMomentum) != 0, died = (what & kOutDied) != 0;
+    if (a.from_main) {
+      const SpeciesView<T>& s0 = a.src[0];
+      const SpeciesView<T>& s1 = a.src[1];
+      if (momentum) {
+        pick(p1, s0.px, s1.px)[i] = O.r.px;
+        pick(p1, s0.py, s1.py)[i] = O.r.py;
+        pick(p1, s0.pz, s1.pz)[i] = O.r.pz;
+      }
+      if (a.positions) {
+        pick(p1, s0.x, s1.x)[i] = O.x[0];
+        pick(p1, s0.y, s1.y)[i] = O.x[1];
+        pick(p1, s0.z, s1.z)[i] = O.x[2];
+      }
+      pick(p1, s0.tau, s1.tau)[i] = O.r.tau;
+      if (died) pick(p1, s0.alive, s1.alive)[i] = 0;
+    } else {
+      using C = RecChunks<T>;
+      rec_store_part<T>(pick(p1, a.src_rec[0], a.src_rec[1]), i, O.r, momentum ? 0 : C::kTau,
+                        (a.write_nev || died) ? C::kCount : C::kTail);
+      if (a.positions) {
+        T* q = pick(p1, a.src_pos[0], a.src_pos[1]) + 4 * i;
+        q[0] = O.x[0];
+        q[1] = O.x[1];
+        q[2] = O.x[2];
+      }
+    }
+  }
+  O.what = 0;
+}
+
+// Final state of a processed photon, stored at once.
 template <typename T>
 __device__ __forceinline__ void store_final(const StepArgs<T>& a, const Lane<T>& L, bool momentum, bool died) {
-  const int64_t i = L.i;
-  if (!L.changed && !died && !(a.write_nev && !a.from_main)) return;  // W = 0 all along: nothing moved
-  if (a.from_main) {
-    const SpeciesView<T>& s = a.src[L.part];
-    if (momentum) {
-      s.px[i] = L.p[0];
-      s.py[i] = L.p[1];
-      s.pz[i] = L.p[2];
-    }
-    if (a.positions) {
-      s.x[i] = L.x[0];
-      s.y[i] = L.x[1];
-      s.z[i] = L.x[2];
-    }
-    s.tau[i] = L.tau;
-    if (died) s.alive[i] = 0;
-    return;
-  }
-  using C = RecChunks<T>;
-  Rec<T> r;
-  r.px = L.p[0];
-  r.py = L.p[1];
-  r.pz = L.p[2];
-  r.tb = L.t0;
-  r.tau = L.tau;
-  r.id = L.id;
-  r.w = L.w;
-  r.root = L.root;
-  r.nev = L.j;
-  r.alive = died ? 0u : 1u;
-  rec_store_part<T>(a.src_rec[L.part], i, r, momentum ? 0 : C::kTau, (a.write_nev || died) ? C::kCount : C::kTail);
-  if (a.positions) {
-    T* q = a.src_pos[L.part] + 4 * i;
-    q[0] = L.x[0];
-    q[1] = L.x[1];
-    q[2] = L.x[2];
-  }
+  Outbox<T> O;
+  O.what = 0;
+  stage_final<T>(a, L, momentum, died, true, O);
+  flush<T>(a, O);
 }
 
 // Tables as the kernels see them: FP32 tables staged in LDS, FP64 in HBM.
@@ -304,7 +414,7 @@ __device__ __forceinline__ void write_child(Rec<T>* out, T* pos, int64_t idx, co
 // has reached the end of the step.
 template <typename T, bool kWrite>
 __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTables& lt, Lane<T>& L, T q,
-                                            int64_t out_base) {
+                                            int64_t out_base, Outbox<T>& O) {
   const T dtT = (T)a.dt;
   if (!(L.t < dtT)) return true;
   const T g = sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
@@ -336,11 +446,23 @@ __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTable
   sample_of<T>(a, lt, 0, chi_e, s_e, u.x, d, omd);
   if (kWrite) {
     const int64_t o = out_base + L.j;
-    if (o < a.out_cap) {
+    if (o < a.out_cap) {  // the photon: k = delta p, born here
       const uint4 v = draw(a.seed, L.id, a.step, (uint32_t)L.j | 0x80000000u);
-      const T k[3] = {d * L.p[0], d * L.p[1], d * L.p[2]};
-      write_child<T>(a.out_rec[0], a.out_pos[0], o, k, L.x, a.positions, L.w, exp_depth_t<T>(u.z),
-                     (uint64_t)v.x | ((uint64_t)v.y << 32), L.root, L.t);
+      O.r.px = d * L.p[0];
+      O.r.py = d * L.p[1];
+      O.r.pz = d * L.p[2];
+      O.r.tb = L.t;
+      O.r.tau = exp_depth_t<T>(u.z);
+      O.r.id = (uint64_t)v.x | ((uint64_t)v.y << 32);
+      O.r.w = L.w;
+      O.r.root = L.root;
+      O.r.nev = 0;
+      O.r.alive = 1u;
+      O.x[0] = L.x[0];
+      O.x[1] = L.x[1];
+      O.x[2] = L.x[2];
+      O.at = o;
+      O.what = kOutChild;
     }
   }
   L.p[0] *= omd;  // collinear recoil: photon k = delta p, lepton (1 - delta) p
@@ -428,45 +550,61 @@ __device__ __forceinline__ LdsTables stage_tables(const StepArgs<T>& a, float* l
 
 // ------------------------------------------------------------------ work distribution
 // Lepton kernels: lanes whose particle has finished take the next one from a
-// queue held by their wave; the wave refills that queue from the launch-wide
-// counter in chunks that shrink as the work runs out (large chunks keep the
-// atomics on the counter rare, small ones at the end balance the tail).
+// queue held by their wave; the wave refills that queue in chunks from a
+// counter.  The particles of the launch are split into kQueueParts contiguous
+// ranges, each with its own counter on its own cache line.  A wave starts on
+// the range of its XCD (work-groups are dealt to the eight XCDs in turn) and
+// moves on to the following ranges once that one is used up.  Device-scope
+// atomics that every wave of the chip sends to one address serialise at the
+// memory side; eight lines and chunks of about remaining / (2 waves of the
+// range), between kChunkMin and kChunkMax, keep that cost small, and the
+// chunks shrink towards the end so the tail stays balanced.
 struct WaveQueue {
   uint64_t next, end;  // wave-uniform
+  uint32_t part, tried;
   bool done;
 };
 
 __device__ __forceinline__ void wq_init(WaveQueue& q) {
   q.next = q.end = 0;
+  q.part = blockIdx.x % kQueueParts;
+  q.tried = 0;
   q.done = false;
 }
 
 // Returns the item index of this lane (>= n: none) for lanes with need set.
+// ctr: kQueueParts counters, kQueueStride words apart, zero at launch.
 __device__ __forceinline__ uint64_t wq_take(WaveQueue& q, bool need, uint64_t n, unsigned long long* ctr,
                                             uint32_t waves) {
   uint64_t m = __ballot(need);
   uint64_t got = ~0ull;
+  const uint64_t waves_part = waves / kQueueParts > 0 ? waves / kQueueParts : 1;
   while (m && !q.done) {
     const uint64_t avail = q.end - q.next;
     if (avail == 0) {
-      // guided chunk: about remaining / (4 waves), at least 64, at most 4096
+      const uint64_t lo = n * q.part / kQueueParts, hi = n * (q.part + 1) / kQueueParts, len = hi - lo;
+      unsigned long long* c = ctr + (size_t)q.part * kQueueStride;
       uint64_t base = 0;
-      uint64_t chunk = 64;
+      uint64_t chunk = kChunkMin;
       if (lane_id() == 0) {
-        const uint64_t seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t rem = seen < n ? n - seen : 0;
-        chunk = rem / (4ull * waves);
-        chunk = chunk < 64 ? 64 : (chunk > 4096 ? 4096 : chunk);
-        base = atomicAdd(ctr, (unsigned long long)chunk);
+        const uint64_t seen = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t rem = seen < len ? len - seen : 0;
+        chunk = rem / (2ull * waves_part);
+        chunk = chunk < kChunkMin ? kChunkMin : (chunk > kChunkMax ? kChunkMax : chunk);
+        base = seen < len ? atomicAdd(c, (unsigned long long)chunk) : len;
       }
       base = readlane64(base, 0);
       chunk = readlane64(chunk, 0);
-      if (base >= n) {
-        q.done = true;
-        break;
+      if (base >= len) {  // this range is used up: go on to the next one
+        if (++q.tried == kQueueParts) {
+          q.done = true;
+          break;
+        }
+        q.part = (q.part + 1) % kQueueParts;
+        continue;
       }
-      q.next = base;
-      q.end = base + chunk < n ? base + chunk : n;
+      q.next = lo + base;
+      q.end = base + chunk < len ? lo + base + chunk : hi;
       continue;
     }
     const uint32_t cnt = (uint32_t)__popcll(m);
@@ -487,31 +625,66 @@ __device__ __forceinline__ uint64_t wq_take(WaveQueue& q, bool need, uint64_t n,
 
 // ------------------------------------------------------------------ count kernels
 // Leptons: event counts vary from 0 to hundreds, so lanes refill.
-template <typename T>
-__global__ void __launch_bounds__(kStepThreads) k_count_lepton(StepArgs<T> a) {
+//
+// Loop trip of a lane (the lepton kernels are a software pipeline): start the
+// next particle if the lane is free and that particle's inputs have arrived;
+// advance the next particle's loads by one stage; take a new next particle
+// once the current one has started; store what the previous trip produced;
+// run one sub-cycle.  A lane so asks for its next particle while it still
+// works on the current one -- its state as soon as the current one starts,
+// the fields of an appended particle (found through its root) one trip later,
+// and in the write kernel the list entry and child offset one trip before the
+// state -- and every load is consumed at least one trip after it was issued.
+// The stores of a trip go out at the start of the next trip, after that
+// trip's loads: global loads and stores retire in issue order, so a store
+// issued just before a wait on a load adds its own latency to that wait.
+constexpr int32_t kNextEmpty = 0;   // nothing taken
+constexpr int32_t kNextIndex = 1;   // list entry and child offset requested (write kernel)
+constexpr int32_t kNextFields = 2;  // state requested, fields still to request
+constexpr int32_t kNextReady = 3;   // all inputs requested
+
+template <typename T, bool kMain>
+__global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1) k_count_lepton(StepArgs<T> a) {
   extern __shared__ float lds[];
   const LdsTables lt = stage_tables<T, false>(a, lds);
   const uint64_t n = (uint64_t)a.n;
   const uint32_t waves = gridDim.x * (kStepThreads / 64);
   WaveQueue wq;
   wq_init(wq);
-  Lane<T> L;
+  Lane<T> L, N;  // the lane's particle and its next one
+  N.x[0] = N.x[1] = N.x[2] = T(0);
+  int32_t next = kNextEmpty;
+  Outbox<T> O;
+  O.what = 0;
   T q = T(-1);  // charge of the lane's particle
   bool have = false;
   int32_t local_max = 0;
   bool capped = false;
   while (true) {
-    const uint64_t k = wq_take(wq, !have, n, &a.queue[0], waves);
-    if (!have && k < n) {
-      load_lane<T>(a, (int64_t)k, L);
+    if (!have && next == kNextReady) {
+      L = N;
       q = a.species + L.part == 0 ? T(-1) : T(1);
       have = true;
+      next = kNextEmpty;
     }
-    if (!__any(have)) break;
-    if (have && lepton_iter<T, false>(a, lt, L, q, 0)) {
-      a.counts[L.k] = L.j;
-      if (a.from_main && a.src[L.part].nev) a.src[L.part].nev[L.i] = L.j;
-      if (L.j == 0) store_final<T>(a, L, a.push != 0, false);
+    if constexpr (!kMain) {
+      if (next == kNextFields) {
+        load_fields<T>(a, N.root, N.E, N.B);
+        next = kNextReady;
+      }
+    }
+    const uint64_t k = wq_take(wq, next == kNextEmpty, n, a.queue, waves);
+    if (next == kNextEmpty && k < n) {
+      load_state<T, kMain>(a, (int64_t)k, N);
+      next = kMain ? kNextReady : kNextFields;
+    }
+    flush<T>(a, O);
+    if (!__any(have || next != kNextEmpty)) break;
+    if (have && lepton_iter<T, false>(a, lt, L, q, 0, O)) {
+      // the event count; the final state only without events (the write kernel
+      // re-runs the others)
+      O.what = kOutCount;
+      stage_final<T>(a, L, a.push != 0, false, L.j == 0, O);
       local_max = L.j > local_max ? L.j : local_max;
       capped |= L.capped;
       have = false;
@@ -636,30 +809,54 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
 }
 
 // ------------------------------------------------------------------ write kernels
-template <typename T>
-__global__ void __launch_bounds__(kStepThreads) k_write_lepton(StepArgs<T> a) {
+template <typename T, bool kMain>
+__global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1) k_write_lepton(StepArgs<T> a) {
   extern __shared__ float lds[];
   const LdsTables lt = stage_tables<T, false>(a, lds);
   const uint64_t n = (uint64_t)*a.list_len;
   const uint32_t waves = gridDim.x * (kStepThreads / 64);
   WaveQueue wq;
   wq_init(wq);
-  Lane<T> L;
+  Lane<T> L, N;  // the lane's particle and its next one (same pipeline as the count kernel)
+  N.x[0] = N.x[1] = N.x[2] = T(0);
+  int32_t next = kNextEmpty;
+  int32_t nk = 0;     // next particle: index in the launch (kept 32-bit until used: no wait on its load)
+  int64_t nbase = 0;  // and the offset of its first child
+  Outbox<T> O;
+  O.what = 0;
   T q = T(-1);  // charge of the lane's particle
   int64_t obase = 0;
   bool have = false;
   while (true) {
-    const uint64_t e = wq_take(wq, !have, n, &a.queue[1], waves);
-    if (!have && e < n) {
-      const int64_t k = a.list[e];
-      load_lane<T>(a, k, L);
+    if (!have && next == kNextReady) {
+      L = N;
+      obase = nbase;
       q = a.species + L.part == 0 ? T(-1) : T(1);
-      obase = a.offsets[e];
       have = true;
+      next = kNextEmpty;
     }
-    if (!__any(have)) break;
-    if (have && lepton_iter<T, true>(a, lt, L, q, obase)) {
-      store_final<T>(a, L, true, false);
+    // each stage acts on the lanes that were in it at the start of the trip;
+    // the list entry goes out before the state loads, whose registers it
+    // does not share
+    const int32_t stage = next;
+    if (!kMain && stage == kNextFields) {
+      load_fields<T>(a, N.root, N.E, N.B);
+      next = kNextReady;
+    }
+    const uint64_t e = wq_take(wq, stage == kNextEmpty, n, a.queue + kQueueWords, waves);
+    if (stage == kNextEmpty && e < n) {
+      nk = a.list[e];
+      nbase = a.offsets[e];
+      next = kNextIndex;
+    }
+    if (stage == kNextIndex) {
+      load_state<T, kMain>(a, (int64_t)nk, N);
+      next = kMain ? kNextReady : kNextFields;
+    }
+    flush<T>(a, O);
+    if (!__any(have || next != kNextEmpty)) break;
+    if (have && lepton_iter<T, true>(a, lt, L, q, obase, O)) {
+      stage_final<T>(a, L, true, false, true, O);
       have = false;
     }
   }
@@ -915,12 +1112,14 @@ hipError_t launch_step_kernel(K kernel, const A& a, int grid, size_t lds, hipStr
 template <typename T, bool kPhoton>
 hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
   if (kPhoton) return launch_step_kernel(&k_count_photon<T>, a, grid, lds, st);
-  return launch_step_kernel(&k_count_lepton<T>, a, grid, lds, st);
+  if (a.from_main) return launch_step_kernel(&k_count_lepton<T, true>, a, grid, lds, st);
+  return launch_step_kernel(&k_count_lepton<T, false>, a, grid, lds, st);
 }
 template <typename T, bool kPhoton>
 hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
   if (kPhoton) return launch_step_kernel(&k_write_photon<T>, a, grid, lds, st);
-  return launch_step_kernel(&k_write_lepton<T>, a, grid, lds, st);
+  if (a.from_main) return launch_step_kernel(&k_write_lepton<T, true>, a, grid, lds, st);
+  return launch_step_kernel(&k_write_lepton<T, false>, a, grid, lds, st);
 }
 hipError_t launch_scan(const ScanArgs& s, hipStream_t st) {
   hipLaunchKernelGGL(k_scan, dim3((unsigned)s.num_tiles), dim3(kScanThreads), 0, st, s);
