@@ -224,9 +224,8 @@ __device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<
 
 // What a lane stores: a child record, or its particle's final state (momentum
 // when it changed, position, optical depth; for records also the event count
-// and alive flag when asked) and, in the count kernel, the event count.  The
-// lepton kernels keep it over to the start of the next loop trip (see the
-// pipeline below); the photon kernels store it at once.
+// and alive flag when asked) and, in the count kernel, the event count;
+// staged in registers by the sub-cycle, stored by flush().
 constexpr uint32_t kOutChild = 1u;     // r is a child record for the append buffer, at = its index
 constexpr uint32_t kOutFinal = 2u;     // r holds the final state of particle `at` of its source
 constexpr uint32_t kOutCount = 4u;     // the event count r.nev goes to counts[k] (and nev[at] of the source)
@@ -625,24 +624,8 @@ __device__ __forceinline__ uint64_t wq_take(WaveQueue& q, bool need, uint64_t n,
 
 // ------------------------------------------------------------------ count kernels
 // Leptons: event counts vary from 0 to hundreds, so lanes refill.
-//
-// Loop trip of a lane (the lepton kernels are a software pipeline): start the
-// next particle if the lane is free and that particle's inputs have arrived;
-// advance the next particle's loads by one stage; take a new next particle
-// once the current one has started; store what the previous trip produced;
-// run one sub-cycle.  A lane so asks for its next particle while it still
-// works on the current one -- its state as soon as the current one starts,
-// the fields of an appended particle (found through its root) one trip later,
-// and in the write kernel the list entry and child offset one trip before the
-// state -- and every load is consumed at least one trip after it was issued.
-// The stores of a trip go out at the start of the next trip, after that
-// trip's loads: global loads and stores retire in issue order, so a store
-// issued just before a wait on a load adds its own latency to that wait.
-constexpr int32_t kNextEmpty = 0;   // nothing taken
-constexpr int32_t kNextIndex = 1;   // list entry and child offset requested (write kernel)
-constexpr int32_t kNextFields = 2;  // state requested, fields still to request
-constexpr int32_t kNextReady = 3;   // all inputs requested
-
+// A particle of the input ensemble (kMain) has its fields at its own index;
+// an appended one finds them through its root, a second load after its record.
 template <typename T, bool kMain>
 __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1) k_count_lepton(StepArgs<T> a) {
   extern __shared__ float lds[];
@@ -651,40 +634,27 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   const uint32_t waves = gridDim.x * (kStepThreads / 64);
   WaveQueue wq;
   wq_init(wq);
-  Lane<T> L, N;  // the lane's particle and its next one
-  N.x[0] = N.x[1] = N.x[2] = T(0);
-  int32_t next = kNextEmpty;
+  Lane<T> L;
   Outbox<T> O;
   O.what = 0;
-  T q = T(-1);  // charge of the lane's particle
+  T q = T(-1);
   bool have = false;
   int32_t local_max = 0;
   bool capped = false;
   while (true) {
-    if (!have && next == kNextReady) {
-      L = N;
+    const uint64_t k = wq_take(wq, !have, n, a.queue, waves);
+    if (!have && k < n) {
+      L.x[0] = L.x[1] = L.x[2] = T(0);
+      load_state<T, kMain>(a, (int64_t)k, L);
+      if (!kMain) load_fields<T>(a, L.root, L.E, L.B);
       q = a.species + L.part == 0 ? T(-1) : T(1);
       have = true;
-      next = kNextEmpty;
     }
-    if constexpr (!kMain) {
-      if (next == kNextFields) {
-        load_fields<T>(a, N.root, N.E, N.B);
-        next = kNextReady;
-      }
-    }
-    const uint64_t k = wq_take(wq, next == kNextEmpty, n, a.queue, waves);
-    if (next == kNextEmpty && k < n) {
-      load_state<T, kMain>(a, (int64_t)k, N);
-      next = kMain ? kNextReady : kNextFields;
-    }
-    flush<T>(a, O);
-    if (!__any(have || next != kNextEmpty)) break;
+    if (!__any(have)) break;
     if (have && lepton_iter<T, false>(a, lt, L, q, 0, O)) {
-      // the event count; the final state only without events (the write kernel
-      // re-runs the others)
       O.what = kOutCount;
       stage_final<T>(a, L, a.push != 0, false, L.j == 0, O);
+      flush<T>(a, O);
       local_max = L.j > local_max ? L.j : local_max;
       capped |= L.capped;
       have = false;
@@ -817,47 +787,29 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   const uint32_t waves = gridDim.x * (kStepThreads / 64);
   WaveQueue wq;
   wq_init(wq);
-  Lane<T> L, N;  // the lane's particle and its next one (same pipeline as the count kernel)
-  N.x[0] = N.x[1] = N.x[2] = T(0);
-  int32_t next = kNextEmpty;
-  int32_t nk = 0;     // next particle: index in the launch (kept 32-bit until used: no wait on its load)
-  int64_t nbase = 0;  // and the offset of its first child
+  Lane<T> L;
   Outbox<T> O;
   O.what = 0;
-  T q = T(-1);  // charge of the lane's particle
+  T q = T(-1);
   int64_t obase = 0;
   bool have = false;
   while (true) {
-    if (!have && next == kNextReady) {
-      L = N;
-      obase = nbase;
+    const uint64_t e = wq_take(wq, !have, n, a.queue + kQueueWords, waves);
+    if (!have && e < n) {
+      const int64_t k = a.list[e];
+      L.x[0] = L.x[1] = L.x[2] = T(0);
+      load_state<T, kMain>(a, k, L);
+      if (!kMain) load_fields<T>(a, L.root, L.E, L.B);
+      obase = a.offsets[e];
       q = a.species + L.part == 0 ? T(-1) : T(1);
       have = true;
-      next = kNextEmpty;
     }
-    // each stage acts on the lanes that were in it at the start of the trip;
-    // the list entry goes out before the state loads, whose registers it
-    // does not share
-    const int32_t stage = next;
-    if (!kMain && stage == kNextFields) {
-      load_fields<T>(a, N.root, N.E, N.B);
-      next = kNextReady;
-    }
-    const uint64_t e = wq_take(wq, stage == kNextEmpty, n, a.queue + kQueueWords, waves);
-    if (stage == kNextEmpty && e < n) {
-      nk = a.list[e];
-      nbase = a.offsets[e];
-      next = kNextIndex;
-    }
-    if (stage == kNextIndex) {
-      load_state<T, kMain>(a, (int64_t)nk, N);
-      next = kMain ? kNextReady : kNextFields;
-    }
-    flush<T>(a, O);
-    if (!__any(have || next != kNextEmpty)) break;
-    if (have && lepton_iter<T, true>(a, lt, L, q, obase, O)) {
-      stage_final<T>(a, L, true, false, true, O);
-      have = false;
+    if (!__any(have)) break;
+    if (have) {
+      const bool fin = lepton_iter<T, true>(a, lt, L, q, obase, O);
+      if (fin) stage_final<T>(a, L, true, false, true, O);
+      flush<T>(a, O);
+      if (fin) have = false;
     }
   }
 }
