@@ -288,10 +288,10 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   a.tab = tab->view;
 
   const int p = photon ? 1 : 0;
-  size_t lds = 0;
+  size_t lds = sizeof(SrcTable);
   if (sizeof(T) == 4)
-    lds = sizeof(float2) * tab->view.rate[p].n +
-          sizeof(float) * tab->view.cdf[p].rows32 * tab->view.cdf[p].cols32;
+    lds += sizeof(float2) * tab->view.rate[p].n +
+           sizeof(float) * tab->view.cdf[p].rows32 * tab->view.cdf[p].cols32;
   // leptons: 2 blocks per CU (the emission tables take ~78 KiB of LDS); photons: 4
   const int max_grid = S->num_cu * (photon ? 4 : 2);
   const int grid = (int)std::min<int64_t>((n + kStepThreads - 1) / kStepThreads, max_grid);

@@ -126,30 +126,88 @@ struct alignas(16) Rec {
 static_assert(sizeof(Rec<float>) == 48, "record layout");
 static_assert(sizeof(Rec<double>) == 64, "record layout");
 
+// A record as its 16-byte chunks, assembled and taken apart field by field (no
+// type punning through memory, so the record stays in registers).
+template <typename T>
+struct RecBits {
+  uint4 c[sizeof(Rec<T>) / 16];
+};
+
+__device__ __forceinline__ uint32_t fbits(float v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ uint32_t lo32(uint64_t v) { return (uint32_t)v; }
+__device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
+__device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
+
+template <typename T>
+__device__ __forceinline__ RecBits<T> rec_pack(const Rec<T>& r) {
+  RecBits<T> b;
+  const uint64_t tau = __builtin_bit_cast(uint64_t, r.tau);
+  const uint4 tail = make_uint4(fbits(r.w), r.root, (uint32_t)r.nev, r.alive);
+  if constexpr (sizeof(T) == 4) {
+    b.c[0] = make_uint4(fbits(r.px), fbits(r.py), fbits(r.pz), fbits(r.tb));
+    b.c[1] = make_uint4(lo32(tau), hi32(tau), lo32(r.id), hi32(r.id));
+    b.c[2] = tail;
+  } else {
+    const uint64_t px = __builtin_bit_cast(uint64_t, r.px), py = __builtin_bit_cast(uint64_t, r.py);
+    const uint64_t pz = __builtin_bit_cast(uint64_t, r.pz), tb = __builtin_bit_cast(uint64_t, r.tb);
+    b.c[0] = make_uint4(lo32(px), hi32(px), lo32(py), hi32(py));
+    b.c[1] = make_uint4(lo32(pz), hi32(pz), lo32(tb), hi32(tb));
+    b.c[2] = make_uint4(lo32(tau), hi32(tau), lo32(r.id), hi32(r.id));
+    b.c[3] = tail;
+  }
+  return b;
+}
+
+template <typename T>
+__device__ __forceinline__ Rec<T> rec_unpack(const RecBits<T>& b) {
+  Rec<T> r;
+  const uint4 tail = b.c[sizeof(T) == 4 ? 2 : 3];
+  const uint4 ti = b.c[sizeof(T) == 4 ? 1 : 2];
+  if constexpr (sizeof(T) == 4) {
+    r.px = __builtin_bit_cast(float, b.c[0].x);
+    r.py = __builtin_bit_cast(float, b.c[0].y);
+    r.pz = __builtin_bit_cast(float, b.c[0].z);
+    r.tb = __builtin_bit_cast(float, b.c[0].w);
+  } else {
+    r.px = __builtin_bit_cast(double, join64(b.c[0].x, b.c[0].y));
+    r.py = __builtin_bit_cast(double, join64(b.c[0].z, b.c[0].w));
+    r.pz = __builtin_bit_cast(double, join64(b.c[1].x, b.c[1].y));
+    r.tb = __builtin_bit_cast(double, join64(b.c[1].z, b.c[1].w));
+  }
+  r.tau = __builtin_bit_cast(double, join64(ti.x, ti.y));
+  r.id = join64(ti.z, ti.w);
+  r.w = __builtin_bit_cast(float, tail.x);
+  r.root = tail.y;
+  r.nev = (int32_t)tail.z;
+  r.alive = tail.w;
+  return r;
+}
+
 template <typename T>
 __device__ __forceinline__ void rec_load(const Rec<T>* base, int64_t i, Rec<T>& r) {
   const uint4* s = reinterpret_cast<const uint4*>(base + i);
-  uint4* d = reinterpret_cast<uint4*>(&r);
+  RecBits<T> b;
 #pragma unroll
-  for (int k = 0; k < (int)(sizeof(Rec<T>) / 16); ++k) d[k] = s[k];
+  for (int k = 0; k < (int)(sizeof(Rec<T>) / 16); ++k) b.c[k] = s[k];
+  r = rec_unpack<T>(b);
 }
 
 template <typename T>
 __device__ __forceinline__ void rec_store(Rec<T>* base, int64_t i, const Rec<T>& r) {
   uint4* d = reinterpret_cast<uint4*>(base + i);
-  const uint4* s = reinterpret_cast<const uint4*>(&r);
+  const RecBits<T> b = rec_pack<T>(r);
 #pragma unroll
-  for (int k = 0; k < (int)(sizeof(Rec<T>) / 16); ++k) d[k] = s[k];
+  for (int k = 0; k < (int)(sizeof(Rec<T>) / 16); ++k) d[k] = b.c[k];
 }
 
 // Stores only the 16-byte chunks [k0, k1) of a record.
 template <typename T>
 __device__ __forceinline__ void rec_store_part(Rec<T>* base, int64_t i, const Rec<T>& r, int k0, int k1) {
   uint4* d = reinterpret_cast<uint4*>(base + i);
-  const uint4* s = reinterpret_cast<const uint4*>(&r);
+  const RecBits<T> b = rec_pack<T>(r);
 #pragma unroll
   for (int k = 0; k < (int)(sizeof(Rec<T>) / 16); ++k)
-    if (k >= k0 && k < k1) d[k] = s[k];
+    if (k >= k0 && k < k1) d[k] = b.c[k];
 }
 
 // chunk indices: momenta (and t_birth) | tau, id | w, root, nev, alive

@@ -33,6 +33,18 @@ constexpr int kStatEventParticles = 2;  // + 0 leptons, + 1 photons
 // the launch is particle begin[0] + k of part 0 for k < n0, else particle
 // begin[1] + k - n0 of part 1, so the append order is that of separate
 // launches for the two species, one after the other.
+// Per-lane choice of launch constants: the step kernels copy the arrays of
+// both source ranges and the fields of the three species into this table in
+// LDS when they start (see step.hip); it precedes the tables in the dynamic LDS.
+enum SrcWord : int { kPx, kPy, kPz, kX, kY, kZ, kW, kTau, kId, kAlive, kNev, kRec, kPos, kBegin, kSrcWords };
+enum FieldWord : int { kEx, kEy, kEz, kBx, kBy, kBz, kStride, kFieldWords };
+struct SrcTable {
+  uint64_t part[2][kSrcWords];    // the two source ranges of the launch
+  uint64_t field[3][kFieldWords];  // the fields of each species
+  uint64_t pad;                    // to a multiple of 16 bytes
+};
+static_assert(sizeof(SrcTable) % 16 == 0, "LDS layout");
+
 template <typename T>
 struct StepArgs {
   SpeciesView<T> src[2];  // the input ensemble of each part (from_main)

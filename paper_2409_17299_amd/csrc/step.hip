@@ -91,35 +91,61 @@ __device__ int64_t lookback(uint64_t* st, int64_t tile, int64_t agg, int64_t bas
 }
 
 // ------------------------------------------------------------------ per-lane choice of launch constants
-// A launch may cover two source ranges, so a lane picks its arrays at run time.
-// Indexing an array of kernel arguments with a per-lane index makes the
-// compiler fetch the element with a vector load from argument memory, which
-// puts a memory round trip in front of every access through the pointer.  The
-// empty asm statements keep each candidate a uniform scalar-register value, so
-// that the choice is a register select.  Pointers pass through the global
-// address space, so that accesses through the result stay global (not flat)
-// memory instructions.
-template <typename V>
-__device__ __forceinline__ V pin_sgpr(V v) {
-  asm("" : "+s"(v));
-  return v;
-}
+// A launch may cover two source ranges, and an appended particle finds its
+// fields through the species of its root, so a lane picks arrays at run time.
+// An array of kernel arguments indexed per lane would be fetched with a global
+// load from argument memory, a memory round trip in front of every access
+// through the pointer, and keeping every candidate in scalar registers spills
+// them; the kernels therefore copy the candidates into a small table in LDS
+// when they start and a lane reads its entry from there.
+// (SrcTable, in step.h, is that table.)
+
+// a pointer from the table, known to address global memory
 template <typename E>
-__device__ __forceinline__ __attribute__((address_space(1))) E* pin_sgpr(E* p) {
-  using G = __attribute__((address_space(1))) E*;
-  G g = (G)p;
-  asm("" : "+s"(g));
-  return g;
+__device__ __forceinline__ E* gptr(uint64_t v) {
+  return (E*)reinterpret_cast<__attribute__((address_space(1))) E*>(v);
 }
-template <typename V>
-__device__ __forceinline__ auto pick(bool second, V a, V b) {
-  const auto x = pin_sgpr(a), y = pin_sgpr(b);
-  return (V)(second ? y : x);
+
+template <typename T>
+__device__ __forceinline__ void fill_part(uint64_t* w, const SpeciesView<T>& s, const Rec<T>* rec, const T* pos,
+                                          int64_t begin) {
+  w[kPx] = (uint64_t)s.px;
+  w[kPy] = (uint64_t)s.py;
+  w[kPz] = (uint64_t)s.pz;
+  w[kX] = (uint64_t)s.x;
+  w[kY] = (uint64_t)s.y;
+  w[kZ] = (uint64_t)s.z;
+  w[kW] = (uint64_t)s.w;
+  w[kTau] = (uint64_t)s.tau;
+  w[kId] = (uint64_t)s.id;
+  w[kAlive] = (uint64_t)s.alive;
+  w[kNev] = (uint64_t)s.nev;
+  w[kRec] = (uint64_t)rec;
+  w[kPos] = (uint64_t)pos;
+  w[kBegin] = (uint64_t)begin;
 }
-template <typename V>
-__device__ __forceinline__ auto pick3(uint32_t which, V a, V b, V c) {
-  const auto x = pin_sgpr(a), y = pin_sgpr(b), z = pin_sgpr(c);
-  return (V)(which == 0 ? x : (which == 1 ? y : z));
+template <typename T>
+__device__ __forceinline__ void fill_field(uint64_t* w, const FieldView<T>& f) {
+  w[kEx] = (uint64_t)f.ex;
+  w[kEy] = (uint64_t)f.ey;
+  w[kEz] = (uint64_t)f.ez;
+  w[kBx] = (uint64_t)f.bx;
+  w[kBy] = (uint64_t)f.by;
+  w[kBz] = (uint64_t)f.bz;
+  w[kStride] = (uint64_t)f.stride;
+}
+
+// one thread per entry (the caller synchronises the block afterwards)
+template <typename T>
+__device__ __forceinline__ void stage_sources(const StepArgs<T>& a, SrcTable* t) {
+  switch (threadIdx.x) {
+    case 0: fill_part<T>(t->part[0], a.src[0], a.src_rec[0], a.src_pos[0], a.begin[0]); break;
+    case 1: fill_part<T>(t->part[1], a.src[1], a.src_rec[1], a.src_pos[1], a.begin[1]); break;
+    case 2: fill_field<T>(t->field[0], a.f[0]); break;
+    case 3: fill_field<T>(t->field[1], a.f[1]); break;
+    case 4: fill_field<T>(t->field[2], a.f[2]); break;
+    default: break;
+  }
 }
 
 // ------------------------------------------------------------------ particle state
@@ -142,29 +168,26 @@ struct Lane {
 // E and B of the particle's root (children keep the fields of the particle
 // they descend from; the fields are constant over the step)
 template <typename T>
-__device__ __forceinline__ void load_fields(const StepArgs<T>& a, uint32_t root, T E[3], T B[3]) {
-  const uint32_t sp = root >> 30;
-  const int64_t idx = (int64_t)(root & 0x3FFFFFFFu);
-  const FieldView<T>& f0 = a.f[0];
-  const FieldView<T>& f1 = a.f[1];
-  const FieldView<T>& f2 = a.f[2];
-  const int64_t o = pick3(sp, f0.stride, f1.stride, f2.stride) ? idx : 0;
-  E[0] = pick3(sp, f0.ex, f1.ex, f2.ex)[o];
-  E[1] = pick3(sp, f0.ey, f1.ey, f2.ey)[o];
-  E[2] = pick3(sp, f0.ez, f1.ez, f2.ez)[o];
-  B[0] = pick3(sp, f0.bx, f1.bx, f2.bx)[o];
-  B[1] = pick3(sp, f0.by, f1.by, f2.by)[o];
-  B[2] = pick3(sp, f0.bz, f1.bz, f2.bz)[o];
+__device__ __forceinline__ void load_fields(const SrcTable* src, uint32_t root, T (&E)[3], T (&B)[3]) {
+  const uint64_t* f = src->field[root >> 30];
+  const int64_t o = f[kStride] ? (int64_t)(root & 0x3FFFFFFFu) : 0;
+  E[0] = gptr<const T>(f[kEx])[o];
+  E[1] = gptr<const T>(f[kEy])[o];
+  E[2] = gptr<const T>(f[kEz])[o];
+  B[0] = gptr<const T>(f[kBx])[o];
+  B[1] = gptr<const T>(f[kBy])[o];
+  B[2] = gptr<const T>(f[kBz])[o];
 }
 
 // Issues the loads of the state of particle k of the launch; a particle of the
 // input ensemble (kMain) also loads its fields, an appended particle finds them
-// through its root afterwards.  Positions load only when they are tracked.
+// through its root afterwards.  Positions are zero unless they are tracked.
 template <typename T, bool kMain>
-__device__ __forceinline__ void load_state(const StepArgs<T>& a, int64_t k, Lane<T>& L) {
+__device__ __forceinline__ void load_state(const StepArgs<T>& a, const SrcTable* src, int64_t k, Lane<T>& L) {
   const bool p1 = k >= a.n0;
   const int part = p1 ? 1 : 0;
-  const int64_t i = pick(p1, a.begin[0], a.begin[1]) + (p1 ? k - a.n0 : k);
+  const uint64_t* w = src->part[part];
+  const int64_t i = (int64_t)w[kBegin] + (p1 ? k - a.n0 : k);
   L.k = k;
   L.i = i;
   L.part = part;
@@ -174,25 +197,25 @@ __device__ __forceinline__ void load_state(const StepArgs<T>& a, int64_t k, Lane
   if constexpr (kMain) {
     // the root is the particle itself: its fields load together with its state
     L.root = ((uint32_t)(a.species + part) << 30) | (uint32_t)i;
-    load_fields<T>(a, L.root, L.E, L.B);
-    const SpeciesView<T>& s0 = a.src[0];
-    const SpeciesView<T>& s1 = a.src[1];
-    L.p[0] = pick(p1, s0.px, s1.px)[i];
-    L.p[1] = pick(p1, s0.py, s1.py)[i];
-    L.p[2] = pick(p1, s0.pz, s1.pz)[i];
+    load_fields<T>(src, L.root, L.E, L.B);
+    L.p[0] = gptr<const T>(w[kPx])[i];
+    L.p[1] = gptr<const T>(w[kPy])[i];
+    L.p[2] = gptr<const T>(w[kPz])[i];
     if (a.positions) {
-      L.x[0] = pick(p1, s0.x, s1.x)[i];
-      L.x[1] = pick(p1, s0.y, s1.y)[i];
-      L.x[2] = pick(p1, s0.z, s1.z)[i];
+      L.x[0] = gptr<const T>(w[kX])[i];
+      L.x[1] = gptr<const T>(w[kY])[i];
+      L.x[2] = gptr<const T>(w[kZ])[i];
+    } else {
+      L.x[0] = L.x[1] = L.x[2] = T(0);
     }
-    L.tau = pick(p1, s0.tau, s1.tau)[i];
-    L.id = pick(p1, s0.id, s1.id)[i];
-    L.w = pick(p1, s0.w, s1.w)[i];
+    L.tau = gptr<const double>(w[kTau])[i];
+    L.id = gptr<const uint64_t>(w[kId])[i];
+    L.w = gptr<const float>(w[kW])[i];
     L.t = T(0);
     L.t0 = T(0);
   } else {
     Rec<T> r;
-    rec_load<T>(pick(p1, a.src_rec[0], a.src_rec[1]), i, r);
+    rec_load<T>(gptr<const Rec<T>>(w[kRec]), i, r);
     L.p[0] = r.px;
     L.p[1] = r.py;
     L.p[2] = r.pz;
@@ -203,22 +226,23 @@ __device__ __forceinline__ void load_state(const StepArgs<T>& a, int64_t k, Lane
     L.w = r.w;
     L.root = r.root;
     if (a.positions) {
-      const T* q = pick(p1, a.src_pos[0], a.src_pos[1]) + 4 * i;
+      const T* q = gptr<const T>(w[kPos]) + 4 * i;
       L.x[0] = q[0];
       L.x[1] = q[1];
       L.x[2] = q[2];
+    } else {
+      L.x[0] = L.x[1] = L.x[2] = T(0);
     }
   }
 }
 
 template <typename T>
-__device__ __forceinline__ void load_lane(const StepArgs<T>& a, int64_t k, Lane<T>& L) {
-  L.x[0] = L.x[1] = L.x[2] = T(0);
+__device__ __forceinline__ void load_lane(const StepArgs<T>& a, const SrcTable* src, int64_t k, Lane<T>& L) {
   if (a.from_main) {
-    load_state<T, true>(a, k, L);
+    load_state<T, true>(a, src, k, L);
   } else {
-    load_state<T, false>(a, k, L);
-    load_fields<T>(a, L.root, L.E, L.B);
+    load_state<T, false>(a, src, k, L);
+    load_fields<T>(src, L.root, L.E, L.B);
   }
 }
 
@@ -267,9 +291,9 @@ __device__ __forceinline__ void stage_final(const StepArgs<T>& a, const Lane<T>&
 }
 
 template <typename T>
-__device__ __forceinline__ void flush(const StepArgs<T>& a, Outbox<T>& O) {
+__device__ __forceinline__ void flush(const StepArgs<T>& a, const SrcTable* src, Outbox<T>& O) {
   const uint32_t what = O.what;
-  const bool p1 = (what & kOutPart1) != 0;
+  const uint64_t* w = src->part[(what & kOutPart1) ? 1 : 0];
   const int64_t i = O.at;
   if (what & kOutChild) {
     rec_store<T>(a.out_rec[0], i, O.r);
@@ -283,34 +307,29 @@ __device__ __forceinline__ void flush(const StepArgs<T>& a, Outbox<T>& O) {
   }
   if (what & kOutCount) {
     a.counts[O.k] = O.r.nev;
-    if (a.from_main) {
-      int32_t* nev = pick(p1, a.src[0].nev, a.src[1].nev);
-      if (nev) nev[i] = O.r.nev;
-    }
+    if (a.from_main && w[kNev]) gptr<int32_t>(w[kNev])[i] = O.r.nev;
   }
   if (what & kOutFinal) {
     const bool momentum = (what & kOutMomentum) != 0, died = (what & kOutDied) != 0;
     if (a.from_main) {
-      const SpeciesView<T>& s0 = a.src[0];
-      const SpeciesView<T>& s1 = a.src[1];
       if (momentum) {
-        pick(p1, s0.px, s1.px)[i] = O.r.px;
-        pick(p1, s0.py, s1.py)[i] = O.r.py;
-        pick(p1, s0.pz, s1.pz)[i] = O.r.pz;
+        gptr<T>(w[kPx])[i] = O.r.px;
+        gptr<T>(w[kPy])[i] = O.r.py;
+        gptr<T>(w[kPz])[i] = O.r.pz;
       }
       if (a.positions) {
-        pick(p1, s0.x, s1.x)[i] = O.x[0];
-        pick(p1, s0.y, s1.y)[i] = O.x[1];
-        pick(p1, s0.z, s1.z)[i] = O.x[2];
+        gptr<T>(w[kX])[i] = O.x[0];
+        gptr<T>(w[kY])[i] = O.x[1];
+        gptr<T>(w[kZ])[i] = O.x[2];
       }
-      pick(p1, s0.tau, s1.tau)[i] = O.r.tau;
-      if (died) pick(p1, s0.alive, s1.alive)[i] = 0;
+      gptr<double>(w[kTau])[i] = O.r.tau;
+      if (died) gptr<uint8_t>(w[kAlive])[i] = 0;
     } else {
       using C = RecChunks<T>;
-      rec_store_part<T>(pick(p1, a.src_rec[0], a.src_rec[1]), i, O.r, momentum ? 0 : C::kTau,
+      rec_store_part<T>(gptr<Rec<T>>(w[kRec]), i, O.r, momentum ? 0 : C::kTau,
                         (a.write_nev || died) ? C::kCount : C::kTail);
       if (a.positions) {
-        T* q = pick(p1, a.src_pos[0], a.src_pos[1]) + 4 * i;
+        T* q = gptr<T>(w[kPos]) + 4 * i;
         q[0] = O.x[0];
         q[1] = O.x[1];
         q[2] = O.x[2];
@@ -322,15 +341,17 @@ __device__ __forceinline__ void flush(const StepArgs<T>& a, Outbox<T>& O) {
 
 // Final state of a processed photon, stored at once.
 template <typename T>
-__device__ __forceinline__ void store_final(const StepArgs<T>& a, const Lane<T>& L, bool momentum, bool died) {
+__device__ __forceinline__ void store_final(const StepArgs<T>& a, const SrcTable* src, const Lane<T>& L,
+                                            bool momentum, bool died) {
   Outbox<T> O;
   O.what = 0;
   stage_final<T>(a, L, momentum, died, true, O);
-  flush<T>(a, O);
+  flush<T>(a, src, O);
 }
 
 // Tables as the kernels see them: FP32 tables staged in LDS, FP64 in HBM.
 struct LdsTables {
+  const SrcTable* src;
   const float2* herm;
   const float* cdf;
 };
@@ -530,7 +551,10 @@ __device__ __forceinline__ bool photon_iter(const StepArgs<T>& a, const LdsTable
 
 template <typename T, bool kPhoton>
 __device__ __forceinline__ LdsTables stage_tables(const StepArgs<T>& a, float* lds) {
-  LdsTables lt{nullptr, nullptr};
+  SrcTable* src = reinterpret_cast<SrcTable*>(lds);
+  stage_sources<T>(a, src);
+  lds += sizeof(SrcTable) / sizeof(float);
+  LdsTables lt{src, nullptr, nullptr};
   if constexpr (sizeof(T) == 4) {
     const int p = kPhoton ? 1 : 0;
     const RateView& r = a.tab.rate[p];
@@ -644,9 +668,8 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   while (true) {
     const uint64_t k = wq_take(wq, !have, n, a.queue, waves);
     if (!have && k < n) {
-      L.x[0] = L.x[1] = L.x[2] = T(0);
-      load_state<T, kMain>(a, (int64_t)k, L);
-      if (!kMain) load_fields<T>(a, L.root, L.E, L.B);
+      load_state<T, kMain>(a, lt.src, (int64_t)k, L);
+      if (!kMain) load_fields<T>(lt.src, L.root, L.E, L.B);
       q = a.species + L.part == 0 ? T(-1) : T(1);
       have = true;
     }
@@ -654,7 +677,7 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
     if (have && lepton_iter<T, false>(a, lt, L, q, 0, O)) {
       O.what = kOutCount;
       stage_final<T>(a, L, a.push != 0, false, L.j == 0, O);
-      flush<T>(a, O);
+      flush<T>(a, lt.src, O);
       local_max = L.j > local_max ? L.j : local_max;
       capped |= L.capped;
       have = false;
@@ -670,14 +693,14 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
 
 // Photons: at most one event each; one photon per thread.
 template <typename T>
-__global__ void __launch_bounds__(kStepThreads) k_count_photon(StepArgs<T> a) {
+__global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1) k_count_photon(StepArgs<T> a) {
   extern __shared__ float lds[];
   const LdsTables lt = stage_tables<T, true>(a, lds);
   int32_t any_event = 0;
   for (int64_t k = (int64_t)blockIdx.x * kStepThreads + threadIdx.x; k < a.n;
        k += (int64_t)gridDim.x * kStepThreads) {
     Lane<T> L;
-    load_lane<T>(a, k, L);
+    load_lane<T>(a, lt.src, k, L);
     if (a.from_main && a.src[0].alive[L.i] == 0) {  // a photon removed earlier is not processed
       a.counts[k] = 0;
       continue;
@@ -685,7 +708,7 @@ __global__ void __launch_bounds__(kStepThreads) k_count_photon(StepArgs<T> a) {
     photon_iter<T, false>(a, lt, L, 0);
     a.counts[k] = L.j;
     if (a.from_main && a.src[0].nev) a.src[0].nev[L.i] = L.j;
-    if (L.j == 0) store_final<T>(a, L, false, false);
+    if (L.j == 0) store_final<T>(a, lt.src, L, false, false);
     any_event |= L.j;
   }
   if (__any(any_event) && lane_id() == 0) atomicMax(&a.stats[kStatMaxEvents], 1ull);
@@ -797,9 +820,8 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
     const uint64_t e = wq_take(wq, !have, n, a.queue + kQueueWords, waves);
     if (!have && e < n) {
       const int64_t k = a.list[e];
-      L.x[0] = L.x[1] = L.x[2] = T(0);
-      load_state<T, kMain>(a, k, L);
-      if (!kMain) load_fields<T>(a, L.root, L.E, L.B);
+      load_state<T, kMain>(a, lt.src, k, L);
+      if (!kMain) load_fields<T>(lt.src, L.root, L.E, L.B);
       obase = a.offsets[e];
       q = a.species + L.part == 0 ? T(-1) : T(1);
       have = true;
@@ -808,23 +830,23 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
     if (have) {
       const bool fin = lepton_iter<T, true>(a, lt, L, q, obase, O);
       if (fin) stage_final<T>(a, L, true, false, true, O);
-      flush<T>(a, O);
+      flush<T>(a, lt.src, O);
       if (fin) have = false;
     }
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kStepThreads) k_write_photon(StepArgs<T> a) {
+__global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1) k_write_photon(StepArgs<T> a) {
   extern __shared__ float lds[];
   const LdsTables lt = stage_tables<T, true>(a, lds);
   const int64_t n = *a.list_len;
   for (int64_t e = (int64_t)blockIdx.x * kStepThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kStepThreads) {
     const int64_t k = a.list[e];
     Lane<T> L;
-    load_lane<T>(a, k, L);
+    load_lane<T>(a, lt.src, k, L);
     photon_iter<T, true>(a, lt, L, a.offsets[e]);
-    store_final<T>(a, L, false, true);  // the photon is removed at its event
+    store_final<T>(a, lt.src, L, false, true);  // the photon is removed at its event
   }
 }
 
