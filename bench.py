@@ -214,7 +214,7 @@ def cascade_bench(sf, torch, steps: int, n_seeds: int) -> dict:
     def report(k, c, st, sec):
         log(f"  step {k}: counts {c}, {st.n_emit} photons, {st.n_pair} pairs, {st.n_rounds} rounds, {sec * 1e3:.1f} ms")
 
-    counts, stats, secs, _ = cascade.run(tables, sp, wl.dt, steps, lambda k: synth.rotating_field(e0, wdt, k), cap,
+    counts, stats, secs, _, _ = cascade.run(tables, sp, wl.dt, steps, lambda k: synth.rotating_field(e0, wdt, k), cap,
                                          app, dtype=torch.float32, seed=0, on_step=report)
     particle_steps = float(counts[:-1].sum())
     events = float(sum(st.n_emit + st.n_pair for st in stats))

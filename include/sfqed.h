@@ -217,6 +217,37 @@ qed_status qed_step(const qed_tables *tab, const qed_step_cfg *cfg, qed_ensemble
  * device-to-host copy). */
 qed_status qed_merge(qed_ensemble *ens, const qed_append app[3], void *stream);
 
+/* Resampling after the merge.  Sec. 4.2 notes that photons too soft ever to
+ * produce a pair need not join the ensemble, and Sec. 5.1 keeps the cascade's
+ * number of macroparticles in check with "global leveling" resampling.
+ *   photon_energy_min: photons with |k|^2 < photon_energy_min^2 (FP64) are
+ *     removed; 0 removes none (2 removes those below the pair threshold);
+ *   target[k]: when species k, after the filter, holds more than target[k]
+ *     particles, it is thinned with one threshold weight w_th solving
+ *     sum_i min(1, w_i / w_th) = target[k]: a particle with w >= w_th stays
+ *     as it is, a lighter one stays when its draw u < w / w_th and then
+ *     weighs w_th (every particle keeps its expected weight).  0: no thinning;
+ *   draws: u = (x + 1/2) 2^-32, x the first word of Philox4x32-10 with
+ *     key = seed and counter (id_lo, id_hi, step, 0xFFFFFFFD).
+ * Survivors keep their order, in place; ens->s[k].count is updated; nev is
+ * not carried.  Blocking (small device-to-host copies for the threshold). */
+typedef struct {
+  double photon_energy_min;
+  int64_t target[3];
+  uint64_t seed;
+  uint32_t step;
+} qed_resample_cfg;
+
+typedef struct {
+  int64_t count_before[3], count_after[3];
+  int64_t filtered;        /* photons removed by the energy filter */
+  double w_threshold[3];   /* leveling threshold weight; 0 where the species was not thinned */
+  int32_t iterations[3];   /* passes of the threshold solve */
+} qed_resample_stats;
+
+void qed_resample_cfg_default(qed_resample_cfg *cfg);  /* no filter, no thinning, seed 0, step 0 */
+qed_status qed_resample(qed_ensemble *ens, const qed_resample_cfg *cfg, qed_resample_stats *stats, void *stream);
+
 /* ------------------------------------------------------------------ kernels of the step, exposed for validation
  * Rates W (per unit time) of one process for given chi and energy (gamma for
  * emission, eps for pairs), evaluated exactly as inside qed_step (FP64:

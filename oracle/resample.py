@@ -8,7 +8,8 @@ leveling" resampling (citing Muraviev et al., Comput. Phys. Commun. 2021).
 The paper gives no formulas; the reading implemented here:
 
 * energy filter: a photon with |k| below e_min (in m_e c) is dropped; with
-  e_min = 2 these are the photons below the pair threshold;
+  e_min = 2 these are the photons below the pair threshold.  The comparison
+  is kx^2 + ky^2 + kz^2 >= e_min^2 in FP64, summed left to right;
 * global leveling of one species to a target count n_t: one threshold weight
   w_th for the whole species.  A particle with w >= w_th stays as it is; one
   with w < w_th stays with probability w / w_th and then carries the weight
@@ -66,7 +67,7 @@ def resample(p, w, ids, seed: int, step: int, n_target: int = 0, e_min: float = 
     w = np.asarray(w, dtype=np.float64)
     keep = np.ones(w.size, dtype=bool)
     if photon and e_min > 0.0:
-        keep = np.sqrt(np.einsum("ij,ij->i", p, p)) >= e_min
+        keep = (p[:, 0] * p[:, 0] + p[:, 1] * p[:, 1]) + p[:, 2] * p[:, 2] >= e_min * e_min
     n_filtered = int((~keep).sum())
     if w_th is None:
         w_th = leveling_threshold(w[keep], n_target)

@@ -88,6 +88,23 @@ class StepStats(C.Structure):
         return d
 
 
+class ResampleCfg(C.Structure):
+    _fields_ = [("photon_energy_min", C.c_double), ("target", C.c_int64 * 3), ("seed", C.c_uint64),
+                ("step", C.c_uint32)]
+
+
+class ResampleStats(C.Structure):
+    _fields_ = [("count_before", C.c_int64 * 3), ("count_after", C.c_int64 * 3), ("filtered", C.c_int64),
+                ("w_threshold", C.c_double * 3), ("iterations", C.c_int32 * 3)]
+
+    def as_dict(self) -> dict:
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if hasattr(v, "__len__") else v
+        return d
+
+
 _lib = None
 
 
@@ -124,6 +141,8 @@ def lib():
             "qed_step": (C.c_int, [v, C.POINTER(StepCfg), C.POINTER(CEnsemble), C.POINTER(CAppend), C.c_double,
                                    C.c_uint64, C.c_uint32, C.POINTER(StepStats), v]),
             "qed_merge": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CAppend), v]),
+            "qed_resample_cfg_default": (None, [C.POINTER(ResampleCfg)]),
+            "qed_resample": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(ResampleCfg), C.POINTER(ResampleStats), v]),
             "qed_eval_rate": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
             "qed_eval_particles": (C.c_int, [v, C.c_int, C.c_int, p, p, p, C.POINTER(CFields), i64, p, p, v]),
             "qed_sample": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
@@ -425,6 +444,27 @@ def merge(main: list, fields: list, app: list, stream=None):
     _check(lib().qed_merge(C.byref(e), a, _stream(stream)))
     for k in range(3):
         main[k].count = int(e.s[k].count)
+
+
+def resample_cfg(photon_energy_min: float = 0.0, target=(0, 0, 0), seed: int = 0, step: int = 0) -> ResampleCfg:
+    cfg = ResampleCfg()
+    lib().qed_resample_cfg_default(C.byref(cfg))
+    cfg.photon_energy_min = float(photon_energy_min)
+    for k in range(3):
+        cfg.target[k] = int(target[k])
+    cfg.seed, cfg.step = int(seed), int(step)
+    return cfg
+
+
+def resample(main: list, fields: list, cfg: ResampleCfg, stream=None) -> ResampleStats:
+    """Photon energy filter and global leveling of the ensemble (after merge);
+    updates the stores' counts."""
+    e = _ensemble(main, fields)
+    st = ResampleStats()
+    _check(lib().qed_resample(C.byref(e), C.byref(cfg), C.byref(st), _stream(stream)))
+    for k in range(3):
+        main[k].count = int(e.s[k].count)
+    return st
 
 
 def eval_rate(tables: Tables, process: int, chi, energy, stream=None):

@@ -6,7 +6,9 @@ moves pointers and counts; every particle operation runs in libsfqed.
 The field of step k comes from a caller's function (for the rotating-field
 cascade: the electric field at the antinode of a rotating standing wave,
 Sec. 5.1), and the growth rate of N(t) ~ e^{Gamma t} is the figure of merit
-(Sec. 5.2).
+(Sec. 5.2).  With resampling (global leveling after every merge, as the paper
+runs its cascade) the number of macroparticles stays bounded and the growth
+shows in the total weight instead.
 """
 from __future__ import annotations
 
@@ -14,15 +16,18 @@ import time
 
 import numpy as np
 
-from . import AppendBuffer, Fields, Store, merge, step, step_cfg
+from . import AppendBuffer, Fields, Store, merge, resample as resample_ensemble, resample_cfg, step, step_cfg
 
 
 def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_capacity, dtype=None, seed: int = 0,
-        cfg=None, on_step=None, stream=None):
+        cfg=None, on_step=None, stream=None, resample=None):
     """species: [(p [n, 3], w [n], tau [n], id [n])] for e-, e+, photons;
     field_of_step(k): the [1, 6] field (ex ey ez bx by bz) shared by all
-    particles during step k.  Returns (counts [steps + 1, 3], per-step stats,
-    seconds per step, the final device stores)."""
+    particles during step k; resample: None, or the keyword arguments of
+    resample_cfg (photon_energy_min, target) applied after every merge, with
+    the cascade's seed and the step index.  Returns (counts [steps + 1, 3],
+    per-step stats, seconds per step, the final device stores, total weight
+    [steps + 1, 3])."""
     import torch
     dtype = dtype or torch.float32
     cfg = cfg if cfg is not None else step_cfg(push=True, nev=False)
@@ -31,7 +36,11 @@ def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_cap
     for m in main:
         m.nev = None
     app = [AppendBuffer(app_capacity[s], dtype) for s in range(3)]
+    def weight():
+        return [float(m.w[:m.count].double().sum()) if m.count else 0.0 for m in main]
+
     counts = [[m.count for m in main]]
+    weights = [weight()]
     stats, secs = [], []
     for k in range(steps):
         f = Fields.from_array(np.asarray(field_of_step(k), dtype=np.float64).reshape(1, 6), dtype)
@@ -41,13 +50,16 @@ def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_cap
         if rc != 0:
             raise RuntimeError(f"cascade step {k}: status {rc}, required capacity {list(st.required_capacity)}")
         merge(main, fields, app, stream=stream)
+        if resample is not None:
+            resample_ensemble(main, fields, resample_cfg(seed=seed, step=k, **resample), stream=stream)
         torch.cuda.synchronize()
         secs.append(time.perf_counter() - t0)
         counts.append([m.count for m in main])
+        weights.append(weight())
         stats.append(st)
         if on_step:
             on_step(k, counts[-1], st, secs[-1])
-    return np.array(counts, dtype=np.int64), stats, secs, main
+    return np.array(counts, dtype=np.int64), stats, secs, main, np.array(weights)
 
 
 def growth_rate(counts: np.ndarray, dt: float, first: int = 0) -> float:

@@ -47,6 +47,7 @@ struct Scratch {
   uint32_t epoch = 0;
   int num_cu = 0;
   size_t max_lds = 0;
+  double* level = nullptr;  // partial sums of the leveling threshold solve
   std::mutex mu;
 };
 
@@ -511,6 +512,101 @@ qed_status merge_impl(qed_ensemble* ens, const qed_append* app, hipStream_t st) 
   return QED_OK;
 }
 
+// Resampling after the merge (qed_resample): per species, the leveling
+// threshold w_th solves sum_i min(1, w_i / w_th) = target.  F(w) = sum_i
+// min(w_i, w) is concave and piecewise linear, so Newton's method on
+// F(w) - target w started right of the root (w_0 = sum_i w_i / target) moves
+// monotonically left and reaches the root of the piece that holds it: each
+// step is w <- S(w) / (target - C(w)), with S the weight below w and C the
+// count at or above it; it stops when w no longer decreases.
+template <typename T>
+qed_status resample_impl(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_resample_stats* out, hipStream_t st) {
+  Scratch* S = scratch_for_current_device();
+  if (!S) return QED_ERR_HIP;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (!S->level) SFQED_HIP(hipMalloc(&S->level, sizeof(double) * (4 * kLevelBlocks + 4)));
+  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
+  qed_resample_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+  const double e_min2 = cfg->photon_energy_min > 0.0 ? cfg->photon_energy_min * cfg->photon_energy_min : 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const int64_t n = ens->s[k].count;
+    stats.count_before[k] = stats.count_after[k] = n;
+    const bool photon = k == 2, filter = photon && e_min2 > 0.0;
+    const int64_t target = cfg->target[k];
+    if (n == 0 || (!filter && target <= 0)) continue;
+    const SpeciesView<T> v = view_of<T>(ens->s[k]);
+    double* part = S->level;
+    double* sums = S->level + 4 * kLevelBlocks;
+    auto level_sums = [&](double wt, double h[4]) -> qed_status {
+      SFQED_HIP(launch_level_sums<T>(v, n, photon ? 1 : 0, e_min2, wt, part, sums, st));
+      SFQED_HIP(hipMemcpyAsync(h, sums, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+      SFQED_HIP(hipStreamSynchronize(st));
+      return QED_OK;
+    };
+    double wt = 0.0;
+    int64_t eligible = n;
+    if (target > 0 || filter) {
+      double h[4];
+      qed_status rc = level_sums(INFINITY, h);  // h: weight below, total weight, count at or above, count
+      if (rc != QED_OK) return rc;
+      eligible = (int64_t)h[3];
+      if (target > 0 && eligible > target) {
+        wt = h[1] / (double)target;
+        for (int it = 0; it < 100; ++it) {
+          if ((rc = level_sums(wt, h)) != QED_OK) return rc;
+          ++stats.iterations[k];
+          const double room = (double)target - h[2];
+          if (!(room > 0.0)) break;
+          const double next = h[0] / room;
+          if (!(next < wt)) break;
+          wt = next;
+        }
+      }
+    }
+    if (photon) stats.filtered = n - eligible;
+    if (wt <= 0.0 && !(filter && eligible < n)) continue;  // nothing to remove
+    const int64_t tiles = (n + kMergeTile - 1) / kMergeTile;
+    if (tiles > S->tiles_cap) {
+      if (S->state_c) {
+        SFQED_HIP(hipDeviceSynchronize());
+        (void)hipFree(S->state_c);
+        (void)hipFree(S->state_f);
+      }
+      SFQED_HIP(hipMalloc(&S->state_c, sizeof(uint64_t) * tiles));
+      SFQED_HIP(hipMalloc(&S->state_f, sizeof(uint64_t) * tiles));
+      SFQED_HIP(hipMemset(S->state_c, 0, sizeof(uint64_t) * tiles));
+      SFQED_HIP(hipMemset(S->state_f, 0, sizeof(uint64_t) * tiles));
+      S->tiles_cap = tiles;
+      S->epoch = 0;
+    }
+    SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t), st));
+    ResampleArgs<T> a;
+    a.s = v;
+    a.n = n;
+    a.photon = photon ? 1 : 0;
+    a.positions = positions ? 1 : 0;
+    a.e_min2 = filter ? e_min2 : 0.0;
+    a.wt = wt;
+    a.seed = cfg->seed;
+    a.step = cfg->step;
+    a.state = S->state_c;
+    a.epoch = next_epoch(S);
+    a.ticket = reinterpret_cast<unsigned long long*>(S->ctrl);
+    a.num_tiles = tiles;
+    a.out_count = reinterpret_cast<int64_t*>(S->ctrl + kMergeCount);
+    SFQED_HIP(launch_resample<T>(a, st));
+    int64_t kept = 0;
+    SFQED_HIP(hipMemcpyAsync(&kept, S->ctrl + kMergeCount, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SFQED_HIP(hipStreamSynchronize(st));
+    ens->s[k].count = kept;
+    stats.count_after[k] = kept;
+    stats.w_threshold[k] = wt;
+  }
+  if (out) *out = stats;
+  return QED_OK;
+}
+
 }  // namespace
 }  // namespace sfqed
 
@@ -679,6 +775,30 @@ qed_status qed_merge(qed_ensemble* ens, const qed_append app[3], void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (ens->dtype == QED_F32) return merge_impl<float>(ens, app, st);
   if (ens->dtype == QED_F64) return merge_impl<double>(ens, app, st);
+  return QED_ERR_ARG;
+}
+
+void qed_resample_cfg_default(qed_resample_cfg* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+}
+
+qed_status qed_resample(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_resample_stats* stats, void* stream) {
+  if (!ens || !cfg) return QED_ERR_ARG;
+  if (!(cfg->photon_energy_min >= 0.0) || !std::isfinite(cfg->photon_energy_min)) {
+    set_error("resample: photon_energy_min must be finite and >= 0");
+    return QED_ERR_ARG;
+  }
+  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
+  for (int s = 0; s < 3; ++s) {
+    if (cfg->target[s] < 0 || !species_ok(ens->s[s], s == 2, positions)) {
+      set_error("resample: invalid species " + std::to_string(s));
+      return QED_ERR_ARG;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ens->dtype == QED_F32) return resample_impl<float>(ens, cfg, stats, st);
+  if (ens->dtype == QED_F64) return resample_impl<double>(ens, cfg, stats, st);
   return QED_ERR_ARG;
 }
 

@@ -102,6 +102,27 @@ struct MergeArgs {
   int64_t* out_count;
 };
 
+// resampling after the merge (see step.hip)
+constexpr int kLevelThreads = 256;
+constexpr int kLevelBlocks = 1024;      // fixed: the sums do not depend on the size of the launch
+constexpr uint32_t kResampleJ = 0xFFFFFFFDu;  // Philox counter word of the thinning draw
+
+template <typename T>
+struct ResampleArgs {
+  SpeciesView<T> s;
+  int64_t n;
+  int32_t photon, positions;
+  double e_min2;  // squared energy threshold of photons (0: no filter)
+  double wt;      // leveling threshold weight (0: no leveling)
+  uint64_t seed;
+  uint32_t step;
+  uint64_t* state;
+  uint32_t epoch;
+  unsigned long long* ticket;
+  int64_t num_tiles;
+  int64_t* out_count;
+};
+
 template <typename T, bool kPhoton>
 hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st);
 template <typename T, bool kPhoton>
@@ -109,6 +130,11 @@ hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t 
 hipError_t launch_scan(const ScanArgs& s, hipStream_t st);
 template <typename T>
 hipError_t launch_merge_photons(const MergeArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_level_sums(const SpeciesView<T>& s, int64_t n, int photon, double e_min2, double wt, double* part,
+                             double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_resample(const ResampleArgs<T>& a, hipStream_t st);
 hipError_t launch_count_alive(const uint8_t* alive, int64_t n, unsigned long long* out, hipStream_t st);
 template <typename T>
 hipError_t launch_count_alive_rec(const Rec<T>* rec, int64_t n, unsigned long long* out, hipStream_t st);

@@ -850,6 +850,166 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   }
 }
 
+// ------------------------------------------------------------------ resampling (after the merge)
+// Photon energy filter (Sec. 4.2: photons too soft ever to produce a pair
+// need not join the ensemble) and global leveling (Sec. 5.1: one threshold
+// weight w_th per species; a particle lighter than w_th stays with probability
+// w / w_th and then weighs w_th, heavier ones stay as they are).  w_th solves
+// sum_i min(1, w_i / w_th) = n_target over the particles that pass the filter;
+// the host finds it from the sums below (api.cpp).
+
+// |k|^2 >= e_min^2 in FP64, summed left to right without contraction
+template <typename T>
+__device__ __forceinline__ bool passes_filter(const SpeciesView<T>& s, int64_t i, bool photon, double e_min2) {
+#pragma clang fp contract(off)
+  if (!photon || !(e_min2 > 0.0)) return true;
+  const double px = s.px[i], py = s.py[i], pz = s.pz[i];
+  return px * px + py * py + pz * pz >= e_min2;
+}
+
+// Per block, over the particles that pass the filter: the weight below wt,
+// the total weight, the count at or above wt, the count; a fixed grid and a
+// fixed reduction order make the sums reproducible.
+template <typename T>
+__global__ void __launch_bounds__(kLevelThreads) k_level_partials(SpeciesView<T> s, int64_t n, int32_t photon,
+                                                                   double e_min2, double wt, double* part) {
+  __shared__ double red[4][kLevelThreads];
+  double bw = 0.0, aw = 0.0, ca = 0.0, ce = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kLevelThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kLevelThreads) {
+    if (!passes_filter<T>(s, i, photon != 0, e_min2)) continue;
+    const double w = s.w[i];
+    ce += 1.0;
+    aw += w;
+    if (w < wt) bw += w;
+    else ca += 1.0;
+  }
+  red[0][threadIdx.x] = bw;
+  red[1][threadIdx.x] = aw;
+  red[2][threadIdx.x] = ca;
+  red[3][threadIdx.x] = ce;
+  __syncthreads();
+  for (int h = kLevelThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kLevelThreads) k_level_total(const double* part, int nblocks, double* out) {
+  __shared__ double red[4][kLevelThreads];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kLevelThreads)
+    for (int q = 0; q < 4; ++q) acc[q] += part[(size_t)b * 4 + q];
+  for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int h = kLevelThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Stable in-place compaction of the survivors (the tile scheme of the photon
+// merge): a particle stays if it passes the filter and, when wt > 0, if
+// w >= wt or its draw u = (x + 1/2) 2^-32 is below w / wt; a light survivor
+// then weighs wt.
+template <typename T>
+__global__ void __launch_bounds__(kMergeThreads) k_resample(ResampleArgs<T> a) {
+  __shared__ int32_t wsum[kMergeThreads / 64];
+  __shared__ int64_t s_tile, s_base;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1ull);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const SpeciesView<T>& s = a.s;
+  T p[kMergeItems][3], x[kMergeItems][3];
+  float w[kMergeItems];
+  double tau[kMergeItems];
+  uint64_t id[kMergeItems];
+  uint32_t okmask = 0;
+#pragma unroll
+  for (int it = 0; it < kMergeItems; ++it) {
+    const int64_t g = tile * kMergeTile + (int64_t)it * kMergeThreads + tid;
+    bool ok = false;
+    if (g < a.n && passes_filter<T>(s, g, a.photon != 0, a.e_min2)) {
+      w[it] = s.w[g];
+      id[it] = s.id[g];
+      ok = true;
+      if (a.wt > 0.0 && (double)w[it] < a.wt) {
+        const double u = ((double)draw(a.seed, id[it], a.step, kResampleJ).x + 0.5) * 0x1p-32;
+        ok = u < (double)w[it] / a.wt;
+        w[it] = (float)a.wt;
+      }
+      if (ok) {
+        p[it][0] = s.px[g];
+        p[it][1] = s.py[g];
+        p[it][2] = s.pz[g];
+        if (a.positions) {
+          x[it][0] = s.x[g];
+          x[it][1] = s.y[g];
+          x[it][2] = s.z[g];
+        }
+        tau[it] = s.tau[g];
+      }
+    }
+    okmask |= (ok ? 1u : 0u) << it;
+  }
+  // every load of the tile must have returned before its aggregate is
+  // published (later tiles write into this tile's range)
+#pragma unroll
+  for (int it = 0; it < kMergeItems; ++it) {
+    if ((okmask >> it) & 1u) {
+      asm volatile("" ::"v"(p[it][0]), "v"(p[it][1]), "v"(p[it][2]), "v"(w[it]), "v"(tau[it]), "v"(id[it])
+                   : "memory");
+      if (a.positions) asm volatile("" ::"v"(x[it][0]), "v"(x[it][1]), "v"(x[it][2]) : "memory");
+    }
+  }
+  int32_t pre[kMergeItems];
+  const int lane = lane_id(), wave = tid >> 6;
+  int32_t tile_total = 0;
+  for (int it = 0; it < kMergeItems; ++it) {
+    const uint64_t m = __ballot((okmask >> it) & 1u);
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int32_t before = 0, all = 0;
+    for (int wv = 0; wv < kMergeThreads / 64; ++wv) {
+      before += wv < wave ? wsum[wv] : 0;
+      all += wsum[wv];
+    }
+    pre[it] = tile_total + before + (int32_t)mbcnt(m);
+    tile_total += all;
+    __syncthreads();
+  }
+  if (tid < 64) {
+    const int64_t b = lookback(a.state, tile, tile_total, 0, a.epoch);
+    if (tid == 0) {
+      s_base = b;
+      if (tile == a.num_tiles - 1) *a.out_count = b + tile_total;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kMergeItems; ++it) {
+    if ((okmask >> it) & 1u) {
+      const int64_t o = s_base + pre[it];
+      s.px[o] = p[it][0];
+      s.py[o] = p[it][1];
+      s.pz[o] = p[it][2];
+      if (a.positions) {
+        s.x[o] = x[it][0];
+        s.y[o] = x[it][1];
+        s.z[o] = x[it][2];
+      }
+      s.w[o] = w[it];
+      s.tau[o] = tau[it];
+      s.id[o] = id[it];
+      if (s.alive) s.alive[o] = 1;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ optical depth of new particles
 template <typename T>
 __global__ void k_init_tau(double* tau, const uint64_t* id, int64_t n, uint64_t seed, uint32_t step) {
@@ -1100,6 +1260,21 @@ hipError_t launch_scan(const ScanArgs& s, hipStream_t st) {
   return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_level_sums(const SpeciesView<T>& s, int64_t n, int photon, double e_min2, double wt, double* part,
+                             double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_level_partials<T>), dim3(kLevelBlocks), dim3(kLevelThreads), 0, st, s, n, photon, e_min2, wt,
+                     part);
+  hipLaunchKernelGGL(k_level_total, dim3(1), dim3(kLevelThreads), 0, st, part, kLevelBlocks, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_resample(const ResampleArgs<T>& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_resample<T>), dim3((unsigned)a.num_tiles), dim3(kMergeThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_merge_photons(const MergeArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_merge_photons<T>), dim3((unsigned)a.num_tiles), dim3(kMergeThreads), 0, st, a);
   return hipGetLastError();
@@ -1167,6 +1342,12 @@ template hipError_t launch_write<float, true>(const StepArgs<float>&, int, size_
 template hipError_t launch_write<double, false>(const StepArgs<double>&, int, size_t, hipStream_t);
 template hipError_t launch_write<double, true>(const StepArgs<double>&, int, size_t, hipStream_t);
 template hipError_t launch_merge_photons<float>(const MergeArgs<float>&, hipStream_t);
+template hipError_t launch_level_sums<float>(const SpeciesView<float>&, int64_t, int, double, double, double*, double*,
+                                             hipStream_t);
+template hipError_t launch_level_sums<double>(const SpeciesView<double>&, int64_t, int, double, double, double*,
+                                              double*, hipStream_t);
+template hipError_t launch_resample<float>(const ResampleArgs<float>&, hipStream_t);
+template hipError_t launch_resample<double>(const ResampleArgs<double>&, hipStream_t);
 template hipError_t launch_merge_photons<double>(const MergeArgs<double>&, hipStream_t);
 template hipError_t launch_init_tau<float>(double*, const uint64_t*, int64_t, uint64_t, uint32_t, hipStream_t);
 template hipError_t launch_count_alive_rec<float>(const Rec<float>*, int64_t, unsigned long long*, hipStream_t);

@@ -35,7 +35,7 @@ def gpu_cascade(torch, sf, tabs, wl, dtype, seed):
     e0, wdt = wl.flags["e0"], wl.flags["omega_dt"]
     sp = [(s.p, s.w, s.tau, s.id) for s in wl.species]
     cap = [SEEDS * 200, SEEDS * 200, SEEDS * 800]
-    counts, stats, secs, _ = cascade.run(tabs, sp, wl.dt, STEPS, lambda k: synth.rotating_field(e0, wdt, k), cap,
+    counts, stats, secs, _, _ = cascade.run(tabs, sp, wl.dt, STEPS, lambda k: synth.rotating_field(e0, wdt, k), cap,
                                          [SEEDS * 60, SEEDS * 60, SEEDS * 250], dtype=dtype, seed=seed)
     return counts
 
@@ -66,3 +66,28 @@ def test_growth_rate_independent_stream(setup):
     eta = abs(go - gg) / go
     print(f"independent streams: Gamma oracle {go:.4e}, gpu {gg:.4e}, eta_Gamma {eta:.2e}")
     assert eta < 2e-2
+
+
+def test_growth_with_global_leveling(setup):
+    """The paper runs its cascade with global leveling after every merge
+    (Sec. 5.1): the number of macroparticles stays near the target while the
+    total weight carries the growth, whose rate must match the unthinned
+    oracle cascade (thinning noise and the changed draws make the comparison
+    statistical: a few per cent)."""
+    torch, sf, tabs, wl, counts_o = setup
+    from paper_2409_17299_amd import cascade
+    e0, wdt = wl.flags["e0"], wl.flags["omega_dt"]
+    sp = [(s.p, s.w, s.tau, s.id) for s in wl.species]
+    target = (20000, 20000, 40000)
+    cap = [SEEDS * 200, SEEDS * 200, SEEDS * 800]
+    counts, _, _, _, weights = cascade.run(tabs, sp, wl.dt, STEPS, lambda k: synth.rotating_field(e0, wdt, k), cap,
+                                           [SEEDS * 60, SEEDS * 60, SEEDS * 250], dtype=torch.float32, seed=0,
+                                           resample=dict(target=target))
+    go = ocascade.growth_rate(counts_o, wl.dt, first=5)
+    gw = ocascade.growth_rate(weights, wl.dt, first=5)
+    eta = abs(go - gw) / go
+    print(f"leveling to {target}: final counts {counts[-1].tolist()} (unthinned oracle {counts_o[-1].tolist()}); "
+          f"Gamma from weight {gw:.4e} vs oracle {go:.4e}, eta {eta:.2e}")
+    assert counts_o[-1][2] > 2 * target[2]          # the unthinned cascade outgrows the target
+    assert np.all(counts[-1] <= np.array(target) * 1.05)
+    assert eta < 3e-2
