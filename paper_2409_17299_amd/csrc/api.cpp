@@ -328,7 +328,11 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   }
   log.end(1, e0);
   e0 = log.begin();
-  e = photon ? launch_write<T, true>(a, grid, lds, st) : launch_write<T, false>(a, grid, lds, st);
+  // The lepton write kernel runs one block per CU (two waves per SIMD): it is
+  // bound by the memory side of its scattered child stores, and half the
+  // waves in flight write as fast.
+  const int wgrid = photon ? grid : (int)std::min<int64_t>((n + kStepThreads - 1) / kStepThreads, S->num_cu);
+  e = photon ? launch_write<T, true>(a, wgrid, lds, st) : launch_write<T, false>(a, wgrid, lds, st);
   if (e != hipSuccess) {
     set_error(std::string("write kernel: ") + hipGetErrorString(e));
     return QED_ERR_HIP;

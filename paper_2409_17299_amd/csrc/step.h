@@ -6,9 +6,10 @@
 namespace sfqed {
 
 // step kernels: 8 waves per block, two blocks per CU (the emission tables take
-// ~78 KiB of LDS per block), so four waves per SIMD; the FP32 lepton kernels
+// ~78 KiB of LDS per block), so four waves per SIMD; the FP32 count kernels
 // are held to the register budget of that occupancy (the FP64 ones keep their
-// tables in HBM and are limited by registers instead).
+// tables in HBM and are limited by registers instead).  The lepton write
+// kernel runs one block per CU.
 constexpr int kStepThreads = 512;
 constexpr int kStepWavesPerSimd = 4;
 // lepton work queue: counters per launch and kernel (see wq_take)

@@ -803,7 +803,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
 
 // ------------------------------------------------------------------ write kernels
 template <typename T, bool kMain>
-__global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1) k_write_lepton(StepArgs<T> a) {
+__global__ void __launch_bounds__(kStepThreads) k_write_lepton(StepArgs<T> a) {
   extern __shared__ float lds[];
   const LdsTables lt = stage_tables<T, false>(a, lds);
   const uint64_t n = (uint64_t)*a.list_len;
