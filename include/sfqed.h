@@ -248,6 +248,64 @@ typedef struct {
 void qed_resample_cfg_default(qed_resample_cfg *cfg);  /* no filter, no thinning, seed 0, step 0 */
 qed_status qed_resample(qed_ensemble *ens, const qed_resample_cfg *cfg, qed_resample_stats *stats, void *stream);
 
+/* ------------------------------------------------------------------ grid fields
+ * Given fields on a grid, the field stage in front of the QED step of a PIC
+ * code (Sec. 5.1: the test problem is a plane wave in a periodic box, with
+ * fields homogeneous across the x axis, so one line of nodes along x holds
+ * them).  Units as everywhere: x in hbar / (m_e c), fields in units of the
+ * Schwinger field.
+ *
+ * qed_grid1d: nx nodes at x_i = x0 + i dx, dx = length / nx, periodic with
+ * period `length`; each node holds all six components (collocated), nx values
+ * per device array, in `dtype`. */
+typedef struct {
+  qed_dtype dtype;
+  int64_t nx;
+  double x0, length;
+  void *ex, *ey, *ez, *bx, *by, *bz;
+} qed_grid1d;
+
+/* Fills the nodes with the standing circularly polarised wave of Sec. 5.1:
+ * with phi = k (x_i - xc),
+ *   E = e0 cos(phi) (0, cos(omega t), sin(omega t)),
+ *   B = e0 sin(phi) (0, cos(omega t), sin(omega t)),
+ * two counter-propagating circularly polarised waves of amplitude e0 / 2 whose
+ * electric field rotates in the y-z plane, with its antinode at xc (a solution
+ * of Maxwell's equations for omega = k).  Evaluated in FP64 (device sin and
+ * cos), rounded once to dtype.  Asynchronous on `stream`. */
+qed_status qed_grid_standing_wave(const qed_grid1d *g, double e0, double k, double omega, double xc, double t,
+                                  void *stream);
+
+/* Periodic box: axis a wraps into [lo[a], lo[a] + len[a]); len[a] = 0 leaves
+ * the axis unwrapped. */
+typedef struct {
+  double lo[3], len[3];
+} qed_box;
+
+/* Per-particle field arrays written by qed_gather_fields (dtype of the
+ * ensemble, capacity >= the species' count); pass them to qed_step as a
+ * qed_fields with stride 1. */
+typedef struct {
+  void *ex, *ey, *ez, *bx, *by, *bz;
+} qed_field_arrays;
+
+/* For every particle of the three species of `ens` (positions required):
+ * 1. wraps each coordinate into the box (FP64, no fused operations):
+ *      s = floor((x - lo) * (1 / len)),  x' = x - s * len,
+ *      x' < lo: x' += len;  x' >= lo + len: x' -= len,
+ *    and stores x' rounded to dtype (a coordinate is written only when that
+ *    changes it);
+ * 2. interpolates the grid linearly at the stored x (FP64, no fused operations):
+ *      u = (x - x0) * (nx / length),  q = floor(u),  f = u - q,
+ *      i = q - nx floor(q / nx) (clamped to [0, nx - 1]),  j = (i + 1) mod nx,
+ *      field = (1 - f) g[i] + f g[j],
+ *    rounded to dtype, into out[s].
+ * The reciprocals 1 / len and nx / length are rounded once.  The grid's dtype
+ * must be the ensemble's.  Returns QED_ERR_ARG for a missing array, a
+ * non-finite or negative box length, or nx < 1.  Asynchronous on `stream`. */
+qed_status qed_gather_fields(qed_ensemble *ens, const qed_grid1d *g, const qed_box *box,
+                             const qed_field_arrays out[3], void *stream);
+
 /* ------------------------------------------------------------------ kernels of the step, exposed for validation
  * Rates W (per unit time) of one process for given chi and energy (gamma for
  * emission, eps for pairs), evaluated exactly as inside qed_step (FP64:

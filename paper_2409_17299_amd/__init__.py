@@ -105,6 +105,19 @@ class ResampleStats(C.Structure):
         return d
 
 
+class CGrid1d(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("nx", C.c_int64), ("x0", C.c_double), ("length", C.c_double)] + \
+               [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")]
+
+
+class CBox(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("len", C.c_double * 3)]
+
+
+class CFieldArrays(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")]
+
+
 _lib = None
 
 
@@ -143,6 +156,10 @@ def lib():
             "qed_merge": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CAppend), v]),
             "qed_resample_cfg_default": (None, [C.POINTER(ResampleCfg)]),
             "qed_resample": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(ResampleCfg), C.POINTER(ResampleStats), v]),
+            "qed_grid_standing_wave": (C.c_int, [C.POINTER(CGrid1d), C.c_double, C.c_double, C.c_double,
+                                                 C.c_double, C.c_double, v]),
+            "qed_gather_fields": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CGrid1d), C.POINTER(CBox),
+                                            C.POINTER(CFieldArrays), v]),
             "qed_eval_rate": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
             "qed_eval_particles": (C.c_int, [v, C.c_int, C.c_int, p, p, p, C.POINTER(CFields), i64, p, p, v]),
             "qed_sample": (C.c_int, [v, C.c_int, C.c_int, p, p, p, i64, v]),
@@ -465,6 +482,69 @@ def resample(main: list, fields: list, cfg: ResampleCfg, stream=None) -> Resampl
     for k in range(3):
         main[k].count = int(e.s[k].count)
     return st
+
+
+# ----------------------------------------------------------------------------- grid fields
+class Grid1d:
+    """Fields at nx nodes x_i = x0 + i length / nx of a periodic line along x
+    (six device arrays of the step's dtype)."""
+
+    def __init__(self, nx: int, x0: float, length: float, dtype=None, device="cuda"):
+        torch = _torch()
+        self.dtype = dtype or torch.float32
+        self.nx, self.x0, self.length = int(nx), float(x0), float(length)
+        self.g = [torch.zeros(max(self.nx, 1), dtype=self.dtype, device=device) for _ in range(6)]
+
+    @classmethod
+    def from_array(cls, nodes, x0: float, length: float, dtype=None, device="cuda"):
+        """nodes: [nx, 6] (ex ey ez bx by bz) on the host."""
+        torch = _torch()
+        nodes = np.asarray(nodes, dtype=np.float64).reshape(-1, 6)
+        g = cls(nodes.shape[0], x0, length, dtype, device)
+        t = torch.as_tensor(nodes).to(device=device, dtype=g.dtype)
+        for k in range(6):
+            g.g[k].copy_(t[:, k])
+        return g
+
+    def c(self) -> CGrid1d:
+        return CGrid1d(_dtype_code(self.dtype), self.nx, self.x0, self.length, *[_ptr(t) for t in self.g])
+
+    def host(self) -> np.ndarray:
+        return np.stack([t[:self.nx].double().cpu().numpy() for t in self.g], axis=1)
+
+
+def box(lo=(0.0, 0.0, 0.0), length=(0.0, 0.0, 0.0)) -> CBox:
+    """Periodic box [lo, lo + length) per axis; length 0 leaves an axis unwrapped."""
+    b = CBox()
+    for k in range(3):
+        b.lo[k], b.len[k] = float(lo[k]), float(length[k])
+    return b
+
+
+def field_buffers(capacity: int, dtype=None, device="cuda") -> Fields:
+    """Per-particle field arrays (stride 1) for gather_fields and step."""
+    torch = _torch()
+    dtype = dtype or torch.float32
+    return Fields(*[torch.zeros(max(int(capacity), 1), dtype=dtype, device=device) for _ in range(6)], stride=1)
+
+
+def standing_wave(grid: Grid1d, e0: float, k: float, omega: float, xc: float, t: float, stream=None):
+    """Nodes of the standing circularly polarised wave at time t (qed_grid_standing_wave)."""
+    g = grid.c()
+    _check(lib().qed_grid_standing_wave(C.byref(g), float(e0), float(k), float(omega), float(xc), float(t),
+                                        _stream(stream)))
+
+
+def gather_fields(main: list, grid: Grid1d, box_: CBox, out: list, stream=None):
+    """Wraps positions into the box and interpolates the grid at them into
+    out[s] (Fields with stride 1, capacity >= count)."""
+    for s in range(3):
+        if main[s].count > 0 and (out[s].stride != 1 or out[s].ex.numel() < main[s].count):
+            raise SfqedError(1, f"gather_fields: output of species {s} holds fewer than {main[s].count} particles")
+    e = _ensemble(main, out)
+    o = (CFieldArrays * 3)(*[CFieldArrays(*[_ptr(t) for t in (f.ex, f.ey, f.ez, f.bx, f.by, f.bz)]) for f in out])
+    g = grid.c()
+    _check(lib().qed_gather_fields(C.byref(e), C.byref(g), C.byref(box_), o, _stream(stream)))
 
 
 def eval_rate(tables: Tables, process: int, chi, energy, stream=None):

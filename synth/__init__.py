@@ -25,6 +25,15 @@ per-particle generator load):
   surrogate samplers, chi log-uniform in a given range.
 * ``static_b_sweep``      electrons and photons with chi* log-uniform in
   [1e-3, 1e3] in a static B perpendicular to the momentum (as the first).
+* ``standing_wave``       the test problem of Sec. 5.1 itself: 2.5e5 seeds
+  (half e-, half e+) at rest, uniform in a periodic cube of one wavelength
+  (800 nm), in a plane standing circularly polarised wave of 6.25e15 V/m
+  whose electric field rotates in the y-z plane, antinode at the centre; the
+  field lives on 128 nodes along x; dt = 0.005 T.  ``standing_wave_nodes``
+  gives the node values at time t.
+
+Lengths are in hbar / (m_e c) (the reduced Compton wavelength) wherever
+positions appear.
 """
 from __future__ import annotations
 
@@ -103,6 +112,7 @@ class Species:
     id: np.ndarray         # [n] uint64, unique over the ensemble
     fields: np.ndarray     # [n, 6] float64 (ex ey ez bx by bz) or [1, 6] shared
     index: np.ndarray      # [n] uint64, index within the species in the full workload
+    x: np.ndarray | None = None  # [n, 3] float64 positions (workloads on a grid), else None
 
     @property
     def n(self) -> int:
@@ -250,3 +260,63 @@ def static_b_sweep(n: int = 200_000_000, seed: int = 0, indices=None, chi_range=
         sp.append(Species(d * pm[:, None], _tau(seed, 55, gidx), np.ones(idx.size), gidx.copy(), f, idx))
     return Workload("static_b_sweep", [sp[0], _empty(), sp[1]], calibration().get("emission_static_b_dt", 1e5),
                     dict(emission=1, pair=1, push=0), "1e8 e- + 1e8 photons, chi* LU[1e-3,1e3], static B")
+
+
+# ----------------------------------------------------------------------------- the standing-wave test problem
+# CODATA 2018: reduced Compton wavelength of the electron (m) and the Schwinger
+# field m_e^2 c^3 / (e hbar) (V/m)
+COMPTON_BAR_M = 3.8615926796e-13
+SCHWINGER_V_PER_M = 1.32328585e18
+
+
+def standing_wave_params(wavelength_m: float = 800e-9, amplitude_v_per_m: float = 6.25e15, nx: int = 128,
+                         dt_over_period: float = 0.005) -> dict:
+    """Geometry and field of the Sec. 5.1 test problem in code units: the box
+    is the cube [-L/2, L/2)^3 of one wavelength L, the electric antinode at the
+    centre; omega = k = 2 pi / L and the period T = L (c = 1)."""
+    length = wavelength_m / COMPTON_BAR_M
+    k = 2.0 * np.pi / length
+    return dict(length=length, x0=-0.5 * length, nx=int(nx), e0=amplitude_v_per_m / SCHWINGER_V_PER_M, k=k, omega=k,
+                xc=0.0, period=length, dt=dt_over_period * length)
+
+
+def standing_wave_nodes(nx: int, x0: float, length: float, e0: float, k: float, omega: float, xc: float,
+                        t: float) -> np.ndarray:
+    """[nx, 6] (ex ey ez bx by bz) at x_i = x0 + i length / nx and time t:
+    E = e0 cos(k (x - xc)) (0, cos wt, sin wt), B = e0 sin(k (x - xc)) (0, cos wt, sin wt)."""
+    x = x0 + np.arange(nx, dtype=np.float64) * (length / nx)
+    phi = k * (x - xc)
+    ce, sb = e0 * np.cos(phi), e0 * np.sin(phi)
+    ct, st = np.cos(omega * t), np.sin(omega * t)
+    out = np.zeros((nx, 6))
+    out[:, 1], out[:, 2] = ce * ct, ce * st
+    out[:, 4], out[:, 5] = sb * ct, sb * st
+    return out
+
+
+def standing_wave(n: int = 250_000, seed: int = 0, indices=None, gamma: float | None = None,
+                  **params) -> Workload:
+    """n seeds, the first half electrons and the rest positrons, uniform in the
+    box; at rest, or (gamma given) with that gamma in random directions.
+    indices: a subset of [0, n) (each index keeps its species and position)."""
+    prm = standing_wave_params(**params)
+    idx = _select(n, indices)
+    half = n // 2
+    length = prm["length"]
+    x = np.stack([(uniform(seed, 50 + a, idx) - 0.5) * length for a in range(3)], axis=1)
+    if gamma is None:
+        p = np.zeros((idx.size, 3))
+    else:
+        p = direction(uniform(seed, 53, idx), uniform(seed, 54, idx)) * np.sqrt(gamma * gamma - 1.0)
+    tau = _tau(seed, 55, idx)
+    sp = []
+    for s, sel in enumerate((idx < half, idx >= half)):
+        sp.append(Species(p[sel], tau[sel], np.ones(int(sel.sum())), idx[sel].copy(), np.zeros((1, 6)),
+                          idx[sel], x[sel]))
+    ph = _empty(True)
+    ph.x = np.zeros((0, 3))
+    sp.append(ph)
+    flags = dict(emission=1, pair=1, push=1, **prm)
+    return Workload("standing_wave", sp, prm["dt"], flags,
+                    f"{n} seeds (e-, e+) {'at rest' if gamma is None else f'gamma {gamma:g}'} in a periodic cube "
+                    "of one wavelength; standing CP wave 6.25e15 V/m on 128 nodes; dt = 0.005 T")

@@ -62,3 +62,18 @@ def test_argument_errors_without_device(L):
     assert L.qed_sample_mlp(None, None, None, None, None, 0, None) == 1
     cfg = sf.default_table_cfg(rad_rows=2)
     assert L.qed_build_rate_tables(C.byref(cfg), None, C.byref(h)) == 1
+
+
+def test_grid_argument_errors_without_device(L):
+    import paper_2409_17299_amd as sf
+    assert L.qed_grid_standing_wave(None, 1.0, 1.0, 1.0, 0.0, 0.0, None) == 1
+    g = sf.CGrid1d(sf.F32, 0, 0.0, 1.0)             # no nodes, no arrays
+    assert L.qed_grid_standing_wave(C.byref(g), 1.0, 1.0, 1.0, 0.0, 0.0, None) == 1
+    assert L.qed_gather_fields(None, None, None, None, None) == 1
+    e = sf.CEnsemble()
+    b = sf.box()
+    out = (sf.CFieldArrays * 3)()
+    assert L.qed_gather_fields(C.byref(e), C.byref(g), C.byref(b), out, None) == 1
+    b_bad = sf.box((0, 0, 0), (float("nan"), 0, 0))
+    g_ok_shape = sf.CGrid1d(sf.F32, 8, 0.0, 1.0, *([C.c_void_p(16)] * 6))  # never dereferenced: the box fails first
+    assert L.qed_gather_fields(C.byref(e), C.byref(g_ok_shape), C.byref(b_bad), out, None) == 1
