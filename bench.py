@@ -231,6 +231,95 @@ def cascade_bench(sf, torch, steps: int, n_seeds: int) -> dict:
                        "ms_per_step_each": [round(x * 1e3, 2) for x in secs]}}
 
 
+# ----------------------------------------------------------------------------- standing-wave test problem
+def standing_wave_bench(sf, torch, steps: int, n_seeds: int, target: int, e_min: float) -> dict:
+    """The test problem of Sec. 5.1 on its grid: n_seeds e-/e+ at rest in a
+    periodic cube of one wavelength, the standing circularly polarised wave
+    filled on the device each step, positions wrapped and fields gathered,
+    qed_step (FP32, push and positions on), qed_merge, then resampling (photons
+    below e_min dropped, global leveling of each species to `target`
+    particles, photons to 4 x target)."""
+    import numpy as np
+
+    import synth
+    from paper_2409_17299_amd import cascade
+    wl = synth.standing_wave(n_seeds)
+    prm = wl.flags
+    dtype = torch.float32
+    tables = sf.Tables()
+    grid = cascade.standing_wave_grid(prm, wl.dt, dtype)
+    sp = [(s.p, s.w, s.tau, s.id, s.x) for s in wl.species]
+    targets = (target, target, 4 * target)
+    cap = [2 * t + n_seeds for t in targets]
+    app = [t for t in targets]
+
+    def report(k, c, st, sec):
+        if k % 50 == 0 or k == steps - 1:
+            log(f"  step {k}: counts {c}, {st.n_emit} photons, {st.n_pair} pairs, {st.n_rounds} rounds, "
+                f"{sec * 1e3:.2f} ms")
+
+    counts, stats, secs, main, weights = cascade.run(tables, sp, wl.dt, steps, None, cap, app, dtype=dtype, seed=0,
+                                                     on_step=report, grid=grid,
+                                                     resample=dict(photon_energy_min=e_min, target=targets))
+    particle_steps = float(counts[:-1].sum())
+    events = float(sum(st.n_emit + st.n_pair for st in stats))
+    t = float(sum(secs))
+    # the gather at the final size, cold: eight copies of the ensemble's
+    # positions (1.7 GB, beyond the 256 MB last-level cache) gathered in turn,
+    # 64 launches captured in one graph (the kernel allocates and clears
+    # nothing) and replayed between two HIP events.  Algorithmic bytes: 12 of
+    # position read and 24 of fields written per particle (positions are
+    # already wrapped, so none is written back).
+    import copy
+    g, box, fill = grid
+    copies, reps = 8, 8
+    sets = []
+    for _ in range(copies):
+        stores = []
+        for m in main:
+            c = copy.copy(m)
+            c.x, c.y, c.z = m.x.clone(), m.y.clone(), m.z.clone()
+            stores.append(c)
+        sets.append((stores, [sf.field_buffers(max(m.count, 1), dtype) for m in main]))
+    n_g = sum(m.count for m in main)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for stores, fb in sets:
+        sf.gather_fields(stores, g, box, fb, stream=side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for _ in range(reps):
+            for stores, fb in sets:
+                sf.gather_fields(stores, g, box, fb, stream=side)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0_, e1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0_.record(side)
+    with torch.cuda.stream(side):
+        graph.replay()
+    e1_.record(side)
+    torch.cuda.synchronize()
+    gms = e0_.elapsed_time(e1_) / (copies * reps)
+    gbps = 36.0 * n_g / (gms * 1e-3) / 1e9
+    del graph, sets
+    wsum = weights.sum(axis=1)
+    gamma_w = float(np.polyfit(np.arange(wsum.size)[steps // 2:] * wl.dt, np.log(wsum[steps // 2:]), 1)[0])
+    return {"metric": METRIC, "value": round(particle_steps / t, 1), "unit": "particle-steps/s",
+            "events_per_s": round(events / t, 1), "n_gpus": 1, "steps": steps, "warmup": 0,
+            "ms_per_step": round(t * 1e3 / steps, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "roofline": {"kernel": "k_gather", "bound": "hbm", "achieved": round(gbps, 1), "peak": 8000.0,
+                         "unit": "GB/s", "frac": round(gbps / 8000.0, 4), "traffic": None,
+                         "particles": n_g, "avg_ms": round(gms, 4), "launches": copies * reps},
+            "config": {"workload": "standing_wave", "seeds": n_seeds, "t_sim_periods": steps * wl.dt / prm["period"],
+                       "dt_over_period": wl.dt / prm["period"], "nx": prm["nx"], "e0": prm["e0"],
+                       "wavelength_m": 800e-9, "targets": list(targets), "photon_energy_min": e_min,
+                       "counts_last": counts[-1].tolist(), "max_particles": int(counts.sum(axis=1).max()),
+                       "growth_rate_weight_per_T": gamma_w * prm["period"],
+                       "ms_per_step_first_last_100": [round(float(np.mean(secs[:100])) * 1e3, 3),
+                                                      round(float(np.mean(secs[-100:])) * 1e3, 3)]}}
+
+
 # ----------------------------------------------------------------------------- precision sweep
 def precision_sweep(sf, torch, n_total: int, chunk: int) -> dict:
     """Rates and first-event energy fractions of n_total/2 electrons and
@@ -310,9 +399,14 @@ def main(argv=None):
     ap.add_argument("--cpu-stride", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--workload", default="crossed_field", choices=["crossed_field", "rotating_e", "static_b_sweep"],
-                    help="rotating_e: the 20-step rotating-field cascade; static_b_sweep: the precision sweep "
+    ap.add_argument("--workload", default="crossed_field",
+                    choices=["crossed_field", "rotating_e", "static_b_sweep", "standing_wave"],
+                    help="rotating_e: the 20-step rotating-field cascade; static_b_sweep: the precision sweep; "
+                         "standing_wave: the standing-wave cascade on its grid over --sw-steps steps "
                          "(instead of the crossed-field step)")
+    ap.add_argument("--sw-steps", type=int, default=1000, help="steps of the standing-wave cascade (0.005 T each)")
+    ap.add_argument("--sw-seeds", type=int, default=250_000)
+    ap.add_argument("--sw-target", type=int, default=1_000_000, help="leveling target per lepton species")
     ap.add_argument("--seeds", type=int, default=1_000_000, help="seed electrons of the rotating_e cascade")
     ap.add_argument("--gamma-min", type=float, default=2.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -333,6 +427,10 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if args.workload == "rotating_e":
         print(json.dumps(cascade_bench(sf, torch, 20, args.seeds)), flush=True)
+        return 0
+    if args.workload == "standing_wave":
+        print(json.dumps(standing_wave_bench(sf, torch, args.sw_steps, args.sw_seeds, args.sw_target, 2.0)),
+              flush=True)
         return 0
     if args.workload == "static_b_sweep":
         print(json.dumps(precision_sweep(sf, torch, 200_000_000, 10_000_000)), flush=True)

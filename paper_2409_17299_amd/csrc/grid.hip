@@ -6,8 +6,9 @@
 //
 // Both kernels are bound by HBM: the gather reads a particle's position and
 // writes its six field components (36 bytes per particle in FP32, 72 in
-// FP64; a position is written back only when the wrap moves it).  The grid
-// itself (a few KB) stays in L2.  Arithmetic is FP64 in a fixed order with no
+// FP64; a position is written back only when the wrap moves it).  A grid of
+// up to kGatherLdsNodes nodes is copied into each block's LDS first, so the
+// interpolation reads it at LDS latency.  Arithmetic is FP64 in a fixed order with no
 // fused operations, so the stored values are a function of the inputs alone.
 
 #include <hip/hip_runtime.h>
@@ -25,6 +26,7 @@ namespace {
 constexpr int kGatherThreads = 256;
 constexpr int kGatherItems = 4;
 constexpr int kGatherTile = kGatherThreads * kGatherItems;
+constexpr int kGatherLdsNodes = 1024;  // grids up to this size are staged in LDS (24 KB FP32, 48 KB FP64)
 
 template <typename T>
 struct GatherSpecies {
@@ -55,41 +57,70 @@ __device__ __forceinline__ double wrap_coord(double x, double lo, double len, do
   return w;
 }
 
+// One particle: wrap its coordinates (v, as loaded), store those that moved,
+// and write the grid's field at its stored x.  g: the six node arrays (LDS or
+// global).
+template <typename T>
+__device__ __forceinline__ void gather_one(const GatherArgs<T>& a, const GatherSpecies<T>& S, const T* const* g,
+                                           int64_t i, const T (&v)[3]) {
+  double xs = 0.0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    T t = v[ax];
+    if (a.wrap[ax]) {
+      t = (T)wrap_coord((double)v[ax], a.lo[ax], a.len[ax], a.rlen[ax], a.hi[ax]);
+      if (t != v[ax]) S.pos[ax][i] = t;
+    }
+    if (ax == 0) xs = (double)t;
+  }
+  const double u = (xs - a.x0) * a.rdx;
+  const double q = floor(u);
+  const double f = u - q;
+  double ic = q - a.nxd * floor(q / a.nxd);
+  ic = fmin(fmax(ic, 0.0), a.nxd - 1.0);  // NaN goes to node 0
+  const int i0 = (int)ic;
+  const int i1 = (double)(i0 + 1) == a.nxd ? 0 : i0 + 1;
+  const double h = 1.0 - f;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) S.out[c][i] = (T)(h * (double)g[c][i0] + f * (double)g[c][i1]);
+}
+
+// Blocks are laid out species by species, kGatherTile particles each; a full
+// tile issues all its position loads before any arithmetic.  Grids of up to
+// kGatherLdsNodes nodes are first copied to LDS.
 template <typename T>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(GatherArgs<T> a) {
-  // the species of a block is uniform: blocks are laid out species by species
+  extern __shared__ __align__(16) unsigned char gather_lds[];  // 6 nx values when nx <= kGatherLdsNodes
+  T* const lds = reinterpret_cast<T*>(gather_lds);
   const int64_t b = blockIdx.x;
   const int sp = b >= a.s[2].first_block ? 2 : (b >= a.s[1].first_block ? 1 : 0);
   const GatherSpecies<T>& S = a.s[sp];
-  const int64_t base = (b - S.first_block) * kGatherTile + threadIdx.x;
-  const int64_t nx = (int64_t)a.nxd;
+  const int nx = (int)a.nxd;
+  const T* g[6];
+  if (nx <= kGatherLdsNodes) {
+    for (int k = threadIdx.x; k < 6 * nx; k += kGatherThreads) lds[k] = a.g[k / nx][k % nx];
+    __syncthreads();
 #pragma unroll
-  for (int it = 0; it < kGatherItems; ++it) {
-    const int64_t i = base + (int64_t)it * kGatherThreads;
-    if (i >= S.n) break;
-    double xs = 0.0;
+    for (int c = 0; c < 6; ++c) g[c] = lds + c * nx;
+  } else {
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const T v = S.pos[ax][i];
-      T t = v;
-      if (a.wrap[ax]) {
-        t = (T)wrap_coord((double)v, a.lo[ax], a.len[ax], a.rlen[ax], a.hi[ax]);
-        if (t != v) S.pos[ax][i] = t;
-      }
-      if (ax == 0) xs = (double)t;
-    }
-    const double u = (xs - a.x0) * a.rdx;
-    const double q = floor(u);
-    const double f = u - q;
-    double ic = q - a.nxd * floor(q / a.nxd);
-    ic = fmin(fmax(ic, 0.0), a.nxd - 1.0);  // NaN goes to node 0
-    const int64_t i0 = (int64_t)ic;
-    const int64_t i1 = i0 + 1 == nx ? 0 : i0 + 1;
-    const double g = 1.0 - f;
+    for (int c = 0; c < 6; ++c) g[c] = a.g[c];
+  }
+  const int64_t tile = (b - S.first_block) * kGatherTile;
+  if (tile + kGatherTile <= S.n) {
+    T v[kGatherItems][3];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const double v = g * (double)a.g[c][i0] + f * (double)a.g[c][i1];
-      S.out[c][i] = (T)v;
+    for (int it = 0; it < kGatherItems; ++it)
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) v[it][ax] = S.pos[ax][tile + threadIdx.x + it * kGatherThreads];
+#pragma unroll
+    for (int it = 0; it < kGatherItems; ++it) gather_one(a, S, g, tile + threadIdx.x + it * kGatherThreads, v[it]);
+  } else {
+    for (int it = 0; it < kGatherItems; ++it) {
+      const int64_t i = tile + threadIdx.x + it * kGatherThreads;
+      if (i >= S.n) break;
+      const T v[3] = {S.pos[0][i], S.pos[1][i], S.pos[2][i]};
+      gather_one(a, S, g, i, v);
     }
   }
 }
@@ -142,6 +173,10 @@ qed_status gather_impl(qed_ensemble* ens, const qed_grid1d& g, const qed_box& bo
   }
   const void* const gv[6] = {g.ex, g.ey, g.ez, g.bx, g.by, g.bz};
   for (int c = 0; c < 6; ++c) a.g[c] = static_cast<const T*>(gv[c]);
+  if (g.nx > 0x7FFFFFFF) {
+    set_error("gather_fields: too many nodes");
+    return QED_ERR_ARG;
+  }
   a.nxd = (double)g.nx;
   a.x0 = g.x0;
   a.rdx = (double)g.nx / g.length;
@@ -157,7 +192,8 @@ qed_status gather_impl(qed_ensemble* ens, const qed_grid1d& g, const qed_box& bo
     set_error("gather_fields: too many particles for one launch");
     return QED_ERR_ARG;
   }
-  hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)blocks), dim3(kGatherThreads), 0, st, a);
+  const size_t lds = g.nx <= kGatherLdsNodes ? 6 * (size_t)g.nx * sizeof(T) : 0;
+  hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)blocks), dim3(kGatherThreads), lds, st, a);
   SFQED_HIP(hipGetLastError());
   return QED_OK;
 }
