@@ -196,6 +196,41 @@ def cpu_baseline(wl_fn, full_n, stride, gamma_min):
                       f"{el:.1f} s)", "events_per_s": (st.n_emit + st.n_pair) / el}
 
 
+def cpu_simd_baseline(full_n, stride, gamma_min, steps=3):
+    """The host-CPU baseline of the paper's own CPU design (Algorithm 3 chunks,
+    vector loops, OpenMP over all host cores; host_simd) on a strided sample of
+    the same workload, FP32 like the GPU step; its tables hold the oracle's
+    values at its nodes.  The best of `steps` timed steps of the same sample."""
+    import numpy as np
+
+    import host_simd
+    import synth
+    from oracle import host_tables
+    nodes = host_tables.nodes(threads=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    tables = host_simd.Tables(nodes, np.float32)
+    counts = [int(round(full_n * 0.4)), int(round(full_n * 0.4))]
+    counts.append(full_n - sum(counts))
+    idx = [np.arange(0, counts[0], stride), np.arange(0, counts[1], stride), np.arange(0, counts[2], stride)]
+    wl = synth.crossed_field(full_n, indices=idx)
+    n = sum(wl.counts)
+    best, st = None, None
+    for _ in range(steps):
+        main = [host_simd.Store.from_arrays(sp.p, sp.w, sp.tau, sp.id, np.float32, photon=s == 2)
+                for s, sp in enumerate(wl.species)]
+        # about 68 photons and 3 pairs per particle in this workload
+        app = [host_simd.Store(c, np.float32, photon=s == 2, appended=True)
+               for s, c in enumerate((n * 10, n * 10, n * 100))]
+        t0 = time.perf_counter()
+        rc, st = host_simd.step(tables, main, [sp.fields for sp in wl.species], app, wl.dt, 0, 0, gamma_min=gamma_min)
+        el = time.perf_counter() - t0
+        assert rc == 0, rc
+        best = el if best is None else min(best, el)
+    return {"value": n / best, "unit": "particle-steps/s", "cores": int(host_simd.lib().hs_max_threads()),
+            "kind": "host_simd", "isa": host_simd.lib().hs_isa().decode(),
+            "sample": f"every {stride}th particle of each species ({n} particles, {st.n_emit + st.n_pair} events, "
+                      f"best of {steps} steps: {best:.2f} s)", "events_per_s": (st.n_emit + st.n_pair) / best}
+
+
 # ----------------------------------------------------------------------------- rotating-field cascade
 def cascade_bench(sf, torch, steps: int, n_seeds: int) -> dict:
     """20 global steps of the rotating-field cascade from n_seeds electrons
@@ -398,6 +433,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--cpu-stride", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--simd-stride", type=int, default=20, help="sample of the host-CPU baseline (host_simd)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--workload", default="crossed_field",
                     choices=["crossed_field", "rotating_e", "static_b_sweep", "standing_wave"],
@@ -525,6 +561,7 @@ def main(argv=None):
     if not args.no_cpu:
         log("CPU baseline: the FP64 oracle on a strided sample")
         out["cpu_baseline"] = cpu_baseline(synth.crossed_field, args.n, args.cpu_stride, args.gamma_min)
+        out["cpu_simd"] = cpu_simd_baseline(args.n, args.simd_stride, args.gamma_min)
     print(json.dumps(out), flush=True)
     return 0
 
