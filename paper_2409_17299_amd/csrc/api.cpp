@@ -31,6 +31,7 @@ constexpr int kListLen = kSlots + 2;
 constexpr int kMergeCount = kSlots + 3;
 constexpr int kAliveCount = kSlots + 4;
 constexpr int kStats = kSlots + 8;      // 8 words
+constexpr int kResampleCount = kSlots + 16;  // 3 words: survivors of each species' compaction
 
 // Library-owned scratch of one device: per-particle counts, offsets and event
 // list of the largest launch so far, look-back words, and a control block.
@@ -522,52 +523,61 @@ qed_status merge_impl(qed_ensemble* ens, const qed_append* app, hipStream_t st) 
 // F(w) - target w started right of the root (w_0 = sum_i w_i / target) moves
 // monotonically left and reaches the root of the piece that holds it: each
 // step is w <- S(w) / (target - C(w)), with S the weight below w and C the
-// count at or above it; it stops when w no longer decreases.
+// count at or above it; it stops when w no longer decreases.  The passes run
+// on the device (k_level_pass keeps the solve's state there): a few are
+// queued for every species, the host reads the three states once, and queues
+// more only for a solve that has not finished (one pass at a time).  The
+// compactions follow, and their counts are read once at the end.
 template <typename T>
 qed_status resample_impl(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_resample_stats* out, hipStream_t st) {
   Scratch* S = scratch_for_current_device();
   if (!S) return QED_ERR_HIP;
   std::lock_guard<std::mutex> lk(S->mu);
-  if (!S->level) SFQED_HIP(hipMalloc(&S->level, sizeof(double) * (4 * kLevelBlocks + 4)));
+  const size_t part_words = 4 * (size_t)kLevelBlocks;
+  if (!S->level) {
+    SFQED_HIP(hipMalloc(&S->level, sizeof(double) * 3 * part_words + sizeof(LevelState) * 3));
+    SFQED_HIP(hipMemset(S->level, 0, sizeof(double) * 3 * part_words + sizeof(LevelState) * 3));
+  }
+  LevelState* dstate = reinterpret_cast<LevelState*>(S->level + 3 * part_words);
   const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
   qed_resample_stats stats;
   std::memset(&stats, 0, sizeof(stats));
   const double e_min2 = cfg->photon_energy_min > 0.0 ? cfg->photon_energy_min * cfg->photon_energy_min : 0.0;
+  bool solve[3] = {false, false, false};
   for (int k = 0; k < 3; ++k) {
     const int64_t n = ens->s[k].count;
     stats.count_before[k] = stats.count_after[k] = n;
-    const bool photon = k == 2, filter = photon && e_min2 > 0.0;
-    const int64_t target = cfg->target[k];
-    if (n == 0 || (!filter && target <= 0)) continue;
+    const bool filter = k == 2 && e_min2 > 0.0;
+    solve[k] = n > 0 && (filter || cfg->target[k] > 0);
+    if (!solve[k]) continue;
     const SpeciesView<T> v = view_of<T>(ens->s[k]);
-    double* part = S->level;
-    double* sums = S->level + 4 * kLevelBlocks;
-    auto level_sums = [&](double wt, double h[4]) -> qed_status {
-      SFQED_HIP(launch_level_sums<T>(v, n, photon ? 1 : 0, e_min2, wt, part, sums, st));
-      SFQED_HIP(hipMemcpyAsync(h, sums, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    const int passes = cfg->target[k] > 0 ? 1 + kLevelDevicePasses : 1;
+    for (int q = 0; q < passes; ++q)
+      SFQED_HIP(launch_level_pass<T>(v, n, k == 2 ? 1 : 0, e_min2, cfg->target[k], q == 0 ? 1 : 0,
+                                     S->level + k * part_words, dstate + k, st));
+  }
+  LevelState ls[3];
+  SFQED_HIP(hipMemcpyAsync(ls, dstate, sizeof(ls), hipMemcpyDeviceToHost, st));
+  SFQED_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < 3; ++k) {
+    if (!solve[k]) continue;
+    const SpeciesView<T> v = view_of<T>(ens->s[k]);
+    while (!ls[k].done && ls[k].iterations < 100) {
+      SFQED_HIP(launch_level_pass<T>(v, ens->s[k].count, k == 2 ? 1 : 0, e_min2, cfg->target[k], 0,
+                                     S->level + k * part_words, dstate + k, st));
+      SFQED_HIP(hipMemcpyAsync(&ls[k], dstate + k, sizeof(LevelState), hipMemcpyDeviceToHost, st));
       SFQED_HIP(hipStreamSynchronize(st));
-      return QED_OK;
-    };
-    double wt = 0.0;
-    int64_t eligible = n;
-    if (target > 0 || filter) {
-      double h[4];
-      qed_status rc = level_sums(INFINITY, h);  // h: weight below, total weight, count at or above, count
-      if (rc != QED_OK) return rc;
-      eligible = (int64_t)h[3];
-      if (target > 0 && eligible > target) {
-        wt = h[1] / (double)target;
-        for (int it = 0; it < 100; ++it) {
-          if ((rc = level_sums(wt, h)) != QED_OK) return rc;
-          ++stats.iterations[k];
-          const double room = (double)target - h[2];
-          if (!(room > 0.0)) break;
-          const double next = h[0] / room;
-          if (!(next < wt)) break;
-          wt = next;
-        }
-      }
     }
+  }
+  bool compacted[3] = {false, false, false};
+  for (int k = 0; k < 3; ++k) {
+    if (!solve[k]) continue;
+    const int64_t n = ens->s[k].count;
+    const bool photon = k == 2, filter = photon && e_min2 > 0.0;
+    const int64_t eligible = (int64_t)ls[k].eligible;
+    const double wt = ls[k].wt;
+    stats.iterations[k] = ls[k].iterations;
+    stats.w_threshold[k] = wt;
     if (photon) stats.filtered = n - eligible;
     if (wt <= 0.0 && !(filter && eligible < n)) continue;  // nothing to remove
     const int64_t tiles = (n + kMergeTile - 1) / kMergeTile;
@@ -586,7 +596,7 @@ qed_status resample_impl(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_res
     }
     SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t), st));
     ResampleArgs<T> a;
-    a.s = v;
+    a.s = view_of<T>(ens->s[k]);
     a.n = n;
     a.photon = photon ? 1 : 0;
     a.positions = positions ? 1 : 0;
@@ -598,14 +608,16 @@ qed_status resample_impl(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_res
     a.epoch = next_epoch(S);
     a.ticket = reinterpret_cast<unsigned long long*>(S->ctrl);
     a.num_tiles = tiles;
-    a.out_count = reinterpret_cast<int64_t*>(S->ctrl + kMergeCount);
+    a.out_count = reinterpret_cast<int64_t*>(S->ctrl + kResampleCount + k);
     SFQED_HIP(launch_resample<T>(a, st));
-    int64_t kept = 0;
-    SFQED_HIP(hipMemcpyAsync(&kept, S->ctrl + kMergeCount, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    compacted[k] = true;
+  }
+  if (compacted[0] || compacted[1] || compacted[2]) {
+    int64_t kept[3] = {0, 0, 0};
+    SFQED_HIP(hipMemcpyAsync(kept, S->ctrl + kResampleCount, sizeof(kept), hipMemcpyDeviceToHost, st));
     SFQED_HIP(hipStreamSynchronize(st));
-    ens->s[k].count = kept;
-    stats.count_after[k] = kept;
-    stats.w_threshold[k] = wt;
+    for (int k = 0; k < 3; ++k)
+      if (compacted[k]) ens->s[k].count = stats.count_after[k] = kept[k];
   }
   if (out) *out = stats;
   return QED_OK;

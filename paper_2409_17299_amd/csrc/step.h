@@ -107,6 +107,17 @@ struct MergeArgs {
 constexpr int kLevelThreads = 256;
 constexpr int kLevelBlocks = 1024;      // fixed: the sums do not depend on the size of the launch
 constexpr uint32_t kResampleJ = 0xFFFFFFFDu;  // Philox counter word of the thinning draw
+constexpr int kLevelDevicePasses = 8;   // threshold passes queued without waiting for the host
+
+// Device state of one species' threshold solve (written by k_level_step, read
+// by the next pass and by the host).
+struct LevelState {
+  double wt;        // current threshold weight (0: no thinning)
+  double eligible;  // particles that pass the filter
+  double total;     // their total weight
+  double pad;
+  int32_t done, iterations;
+};
 
 template <typename T>
 struct ResampleArgs {
@@ -132,8 +143,8 @@ hipError_t launch_scan(const ScanArgs& s, hipStream_t st);
 template <typename T>
 hipError_t launch_merge_photons(const MergeArgs<T>& a, hipStream_t st);
 template <typename T>
-hipError_t launch_level_sums(const SpeciesView<T>& s, int64_t n, int photon, double e_min2, double wt, double* part,
-                             double* out, hipStream_t st);
+hipError_t launch_level_pass(const SpeciesView<T>& s, int64_t n, int photon, double e_min2, int64_t target, int first,
+                             double* part, LevelState* ls, hipStream_t st);
 template <typename T>
 hipError_t launch_resample(const ResampleArgs<T>& a, hipStream_t st);
 hipError_t launch_count_alive(const uint8_t* alive, int64_t n, unsigned long long* out, hipStream_t st);

@@ -867,13 +867,25 @@ __device__ __forceinline__ bool passes_filter(const SpeciesView<T>& s, int64_t i
   return px * px + py * py + pz * pz >= e_min2;
 }
 
-// Per block, over the particles that pass the filter: the weight below wt,
-// the total weight, the count at or above wt, the count; a fixed grid and a
-// fixed reduction order make the sums reproducible.
+// One pass of the threshold solve, in two kernels.  k_level_partials: per
+// block, over the particles that pass the filter, the weight below wt, the
+// total weight, the count at or above wt and the count (a fixed grid and a
+// fixed reduction order make the sums reproducible).  k_level_step: one block
+// adds the blocks' sums in block order and takes the next step of the solve:
+//   first pass (wt = infinity): w_0 = total weight / target when more than
+//     `target` particles pass the filter, else done with wt = 0;
+//   later passes: w <- S(w) / (target - C(w)), done when that no longer
+//     decreases w (or target - C(w) <= 0).
+// The state stays on the device and both kernels return at once when the
+// solve is done, so a fixed number of passes can be queued without waiting
+// for the host; the kernel boundary orders the sums before their total.
 template <typename T>
 __global__ void __launch_bounds__(kLevelThreads) k_level_partials(SpeciesView<T> s, int64_t n, int32_t photon,
-                                                                   double e_min2, double wt, double* part) {
+                                                                   double e_min2, int32_t first, const LevelState* ls,
+                                                                   double* part) {
   __shared__ double red[4][kLevelThreads];
+  if (!first && ls->done) return;
+  const double wt = first ? INFINITY : ls->wt;
   double bw = 0.0, aw = 0.0, ca = 0.0, ce = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kLevelThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kLevelThreads) {
     if (!passes_filter<T>(s, i, photon != 0, e_min2)) continue;
@@ -896,8 +908,11 @@ __global__ void __launch_bounds__(kLevelThreads) k_level_partials(SpeciesView<T>
   if (threadIdx.x < 4) part[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void __launch_bounds__(kLevelThreads) k_level_total(const double* part, int nblocks, double* out) {
+__global__ void __launch_bounds__(kLevelThreads) k_level_step(const double* part, int nblocks, int32_t first,
+                                                               double target, LevelState* ls) {
   __shared__ double red[4][kLevelThreads];
+  if (!first && ls->done) return;
+  const double wt = first ? INFINITY : ls->wt;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += kLevelThreads)
     for (int q = 0; q < 4; ++q) acc[q] += part[(size_t)b * 4 + q];
@@ -908,7 +923,32 @@ __global__ void __launch_bounds__(kLevelThreads) k_level_total(const double* par
       for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x != 0) return;
+  const double below = red[0][0], total = red[1][0], above = red[2][0], count = red[3][0];
+  if (first) {
+    ls->eligible = count;
+    ls->total = total;
+    ls->iterations = 0;
+    if (target > 0.0 && count > target) {
+      ls->wt = total / target;
+      ls->done = 0;
+    } else {
+      ls->wt = 0.0;
+      ls->done = 1;
+    }
+    return;
+  }
+  ls->iterations += 1;
+  const double room = target - above;
+  if (!(room > 0.0)) {
+    ls->done = 1;
+  } else {
+    const double next = below / room;
+    if (next < wt)
+      ls->wt = next;
+    else
+      ls->done = 1;
+  }
 }
 
 // Stable in-place compaction of the survivors (the tile scheme of the photon
@@ -1260,11 +1300,11 @@ hipError_t launch_scan(const ScanArgs& s, hipStream_t st) {
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_level_sums(const SpeciesView<T>& s, int64_t n, int photon, double e_min2, double wt, double* part,
-                             double* out, hipStream_t st) {
-  hipLaunchKernelGGL((k_level_partials<T>), dim3(kLevelBlocks), dim3(kLevelThreads), 0, st, s, n, photon, e_min2, wt,
-                     part);
-  hipLaunchKernelGGL(k_level_total, dim3(1), dim3(kLevelThreads), 0, st, part, kLevelBlocks, out);
+hipError_t launch_level_pass(const SpeciesView<T>& s, int64_t n, int photon, double e_min2, int64_t target, int first,
+                             double* part, LevelState* ls, hipStream_t st) {
+  hipLaunchKernelGGL((k_level_partials<T>), dim3(kLevelBlocks), dim3(kLevelThreads), 0, st, s, n, photon, e_min2,
+                     first, ls, part);
+  hipLaunchKernelGGL(k_level_step, dim3(1), dim3(kLevelThreads), 0, st, part, kLevelBlocks, first, (double)target, ls);
   return hipGetLastError();
 }
 
@@ -1342,10 +1382,10 @@ template hipError_t launch_write<float, true>(const StepArgs<float>&, int, size_
 template hipError_t launch_write<double, false>(const StepArgs<double>&, int, size_t, hipStream_t);
 template hipError_t launch_write<double, true>(const StepArgs<double>&, int, size_t, hipStream_t);
 template hipError_t launch_merge_photons<float>(const MergeArgs<float>&, hipStream_t);
-template hipError_t launch_level_sums<float>(const SpeciesView<float>&, int64_t, int, double, double, double*, double*,
-                                             hipStream_t);
-template hipError_t launch_level_sums<double>(const SpeciesView<double>&, int64_t, int, double, double, double*,
-                                              double*, hipStream_t);
+template hipError_t launch_level_pass<float>(const SpeciesView<float>&, int64_t, int, double, int64_t, int, double*,
+                                                LevelState*, hipStream_t);
+template hipError_t launch_level_pass<double>(const SpeciesView<double>&, int64_t, int, double, int64_t, int,
+                                                 double*, LevelState*, hipStream_t);
 template hipError_t launch_resample<float>(const ResampleArgs<float>&, hipStream_t);
 template hipError_t launch_resample<double>(const ResampleArgs<double>&, hipStream_t);
 template hipError_t launch_merge_photons<double>(const MergeArgs<double>&, hipStream_t);
