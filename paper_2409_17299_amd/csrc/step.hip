@@ -715,22 +715,42 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
 }
 
 // ------------------------------------------------------------------ scan kernel
+// One tile of kScanTile counts per block: thread t holds items
+// [16 t, 16 t + 16) of the tile (loaded as four 16-byte vectors when the tile
+// is full).  The tile's event particles and their first child offsets are
+// compacted into LDS relative to the tile while the two look-backs (children
+// on wave 0, event particles on wave 1) run, then written out by the whole
+// block, consecutive threads to consecutive entries.
 __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
   __shared__ int64_t sc[kScanThreads / 64];
   __shared__ int32_t sf[kScanThreads / 64];
   __shared__ int64_t s_tile, s_base_c, s_base_f;
+  __shared__ int64_t l_off[kScanTile];
+  __shared__ int32_t l_idx[kScanTile];
   const int tid = threadIdx.x;
   if (tid == 0) s_tile = (int64_t)atomicAdd(s.ticket, 1ull);
   __syncthreads();
   const int64_t tile = s_tile;
   const int64_t k0 = tile * kScanTile + (int64_t)tid * kScanItems;
   int32_t c[kScanItems];
+  if (k0 + kScanItems <= s.n) {
+    const int4* v = reinterpret_cast<const int4*>(s.counts + k0);
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; ++q) {
+      const int4 x = v[q];
+      c[4 * q] = x.x;
+      c[4 * q + 1] = x.y;
+      c[4 * q + 2] = x.z;
+      c[4 * q + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) c[i] = k0 + i < s.n ? s.counts[k0 + i] : 0;
+  }
   int64_t my_c = 0;
   int32_t my_f = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const int64_t k = k0 + i;
-    c[i] = k < s.n ? s.counts[k] : 0;
     my_c += c[i];
     my_f += c[i] > 0;
   }
@@ -752,52 +772,44 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
     sf[wave] = inf;
   }
   __syncthreads();
-  if (tid < 64) {
-    int64_t acc_c = 0;
-    int32_t acc_f = 0;
-    for (int wv = 0; wv < kScanThreads / 64; ++wv) {
-      acc_c += sc[wv];
-      acc_f += sf[wv];
-    }
-    const int64_t base = (tile == 0 && tid == 0) ? *s.cursor : 0;
-    const int64_t b0 = __shfl(base, 0);
-    const int64_t bc = lookback(s.state_c, tile, acc_c, b0, s.epoch);
-    const int64_t bf = lookback(s.state_f, tile, acc_f, 0, s.epoch);
-    if (tid == 0) {
-      s_base_c = bc;
-      s_base_f = bf;
-      if (tile == s.num_tiles - 1) {
-        *s.cursor = bc + acc_c;
-        *s.list_len = bf + acc_f;
-        atomicAdd(s.event_particles, (unsigned long long)(bf + acc_f));
-      }
-    }
+  int64_t pre_c = 0, acc_c = 0;
+  int32_t pre_f = 0, acc_f = 0;
+  for (int wv = 0; wv < kScanThreads / 64; ++wv) {
+    pre_c += wv < wave ? sc[wv] : 0;
+    pre_f += wv < wave ? sf[wv] : 0;
+    acc_c += sc[wv];
+    acc_f += sf[wv];
   }
-  __syncthreads();
-  if (tid == 0) {
-    int64_t acc_c = 0;
-    int32_t acc_f = 0;
-    for (int wv = 0; wv < kScanThreads / 64; ++wv) {
-      const int64_t tc = sc[wv];
-      const int32_t tf = sf[wv];
-      sc[wv] = acc_c;
-      sf[wv] = acc_f;
-      acc_c += tc;
-      acc_f += tf;
-    }
-  }
-  __syncthreads();
-  int64_t oc = s_base_c + sc[wave] + ic - my_c;
-  int32_t of = (int32_t)(s_base_f + sf[wave] + inf - my_f);
+  // the tile's event particles, compacted relative to the tile
+  int64_t lc = pre_c + ic - my_c;
+  int32_t lf = pre_f + inf - my_f;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const int64_t k = k0 + i;
-    if (k < s.n && c[i] > 0) {  // event particles: index and first child offset, in order
-      s.list[of] = (int32_t)k;
-      s.offsets[of] = oc;
-      ++of;
+    if (c[i] > 0) {
+      l_idx[lf] = (int32_t)(k0 + i);
+      l_off[lf] = lc;
+      ++lf;
     }
-    oc += c[i];
+    lc += c[i];
+  }
+  if (wave == 0) {
+    const int64_t base = (tile == 0 && lane == 0) ? *s.cursor : 0;
+    const int64_t bc = lookback(s.state_c, tile, acc_c, __shfl(base, 0), s.epoch);
+    if (lane == 0) s_base_c = bc;
+  } else if (wave == 1) {
+    const int64_t bf = lookback(s.state_f, tile, acc_f, 0, s.epoch);
+    if (lane == 0) s_base_f = bf;
+  }
+  __syncthreads();
+  const int64_t bc = s_base_c, bf = s_base_f;
+  if (tid == 0 && tile == s.num_tiles - 1) {
+    *s.cursor = bc + acc_c;
+    *s.list_len = bf + acc_f;
+    atomicAdd(s.event_particles, (unsigned long long)(bf + acc_f));
+  }
+  for (int j = tid; j < acc_f; j += kScanThreads) {
+    s.list[bf + j] = l_idx[j];
+    s.offsets[bf + j] = bc + l_off[j];
   }
 }
 
