@@ -3,10 +3,12 @@
 
 A step is one global time step of the crossed-field workload through the whole
 hot path: restore the 1e7-particle input ensemble into the working buffers
-(device copies), qed_step (chi, rates, optical-depth sub-cycling, inverse-CDF
-sampling, recoil, deterministic append, every generation of secondaries), and
-qed_merge (drop photons that made pairs, append the children).  Inputs are
-resident in HBM before timing starts.
+(device copies), then the step and the merge in one qed_step_merged call (chi,
+rates, optical-depth sub-cycling, inverse-CDF sampling, recoil, deterministic
+append, every generation of secondaries; photons that made pairs dropped and
+the children merged into the ensemble).  --two-call times qed_step followed by
+qed_merge instead, with identical results.  Inputs are resident in HBM before
+timing starts.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -105,8 +107,13 @@ class DeviceWorkload:
                 dst.alive[:n].fill_(1)
             dst.count = n
 
-    def step(self, tables, index, cfg):
+    def step(self, tables, index, cfg, merged=True):
+        """restore, then the step and the merge: one qed_step_merged call, or
+        qed_step followed by qed_merge (identical results)."""
         self.restore()
+        if merged:
+            return self.sf.step_merged(tables, self.main, self.fields, self.app, self.wl.dt, 0, index, cfg,
+                                       check=False)
         rc, st = self.sf.step(tables, self.main, self.fields, self.app, self.wl.dt, 0, index, cfg, check=False)
         if rc != 0:
             return rc, st
@@ -435,6 +442,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--simd-stride", type=int, default=20, help="sample of the host-CPU baseline (host_simd)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--two-call", action="store_true",
+                    help="time qed_step followed by qed_merge instead of qed_step_merged (same results)")
     ap.add_argument("--workload", default="crossed_field",
                     choices=["crossed_field", "rotating_e", "static_b_sweep", "standing_wave"],
                     help="rotating_e: the 20-step rotating-field cascade; static_b_sweep: the precision sweep; "
@@ -491,7 +500,7 @@ def main(argv=None):
     caps = [int(args.n * 12), int(args.n * 12), int(min(args.n * 100, (1 << 30) - 1024))]
     while True:
         dw = DeviceWorkload(sf, torch, wl, caps, dtype)
-        rc, st = dw.step(tables, 10_000, cfg)
+        rc, st = dw.step(tables, 10_000, cfg, merged=not args.two_call)
         if rc == 0:
             break
         if rc != 2:
@@ -508,14 +517,14 @@ def main(argv=None):
     log(f"  capacities {caps}")
 
     for i in range(args.warmup):
-        rc, st = dw.step(tables, i, cfg)
+        rc, st = dw.step(tables, i, cfg, merged=not args.two_call)
         assert rc == 0, rc
         log(f"warmup step {i}: {st.n_emit} photons, {st.n_pair} pairs, {st.n_rounds} rounds")
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        rc, st = dw.step(tables, args.warmup + i, cfg)
+        rc, st = dw.step(tables, args.warmup + i, cfg, merged=not args.two_call)
         assert rc == 0, rc
         stats.append(st)
     torch.cuda.synchronize()

@@ -217,6 +217,20 @@ qed_status qed_step(const qed_tables *tab, const qed_step_cfg *cfg, qed_ensemble
  * device-to-host copy). */
 qed_status qed_merge(qed_ensemble *ens, const qed_append app[3], void *stream);
 
+/* qed_step followed by qed_merge, with the photons merged inside the step
+ * (Algorithm 2, then the merge of Sec. 4.2): the input photons are compacted
+ * once their round is done, and every appended photon that survives the step
+ * is written straight into ens->s[2] by the pass that decides it has no pair
+ * event, instead of being read back from its record by the merge.  The
+ * resulting ensemble (arrays, order, counts) is identical to qed_step then
+ * qed_merge; app[0..1] and app[2] hold the appended records as qed_step
+ * leaves them, except that app[2]'s records keep the state the photons were
+ * emitted with (their final states are in ens->s[2]).  Capacity of ens->s[k]
+ * must hold the merged result: on QED_ERR_CAPACITY nothing is written past
+ * it and the ensemble is partly advanced (the caller restores it). */
+qed_status qed_step_merged(const qed_tables *tab, const qed_step_cfg *cfg, qed_ensemble *ens, qed_append app[3],
+                           double dt, uint64_t seed, uint32_t step, qed_step_stats *stats, void *stream);
+
 /* Resampling after the merge.  Sec. 4.2 notes that photons too soft ever to
  * produce a pair need not join the ensemble, and Sec. 5.1 keeps the cascade's
  * number of macroparticles in check with "global leveling" resampling.

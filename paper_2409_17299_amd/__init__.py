@@ -154,6 +154,8 @@ def lib():
             "qed_step": (C.c_int, [v, C.POINTER(StepCfg), C.POINTER(CEnsemble), C.POINTER(CAppend), C.c_double,
                                    C.c_uint64, C.c_uint32, C.POINTER(StepStats), v]),
             "qed_merge": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CAppend), v]),
+            "qed_step_merged": (C.c_int, [v, C.POINTER(StepCfg), C.POINTER(CEnsemble), C.POINTER(CAppend),
+                                          C.c_double, C.c_uint64, C.c_uint32, C.POINTER(StepStats), v]),
             "qed_resample_cfg_default": (None, [C.POINTER(ResampleCfg)]),
             "qed_resample": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(ResampleCfg), C.POINTER(ResampleStats), v]),
             "qed_grid_standing_wave": (C.c_int, [C.POINTER(CGrid1d), C.c_double, C.c_double, C.c_double,
@@ -450,6 +452,26 @@ def step(tables: Tables, main: list, fields: list, app: list, dt: float, seed: i
                         C.c_uint32(step_index), C.byref(st), _stream(stream))
     for k in range(3):
         app[k].count = int(a[k].count)
+    if check:
+        _check(rc)
+    return rc, st
+
+
+def step_merged(tables: Tables, main: list, fields: list, app: list, dt: float, seed: int, step_index: int,
+                cfg: StepCfg | None = None, stream=None, check: bool = True) -> tuple[int, StepStats]:
+    """step() then merge() in one call, the photons merged inside the step
+    (qed_step_merged); updates main counts and app counts."""
+    cfg = cfg if cfg is not None else step_cfg()
+    e = _ensemble(main, fields)
+    for s in app:
+        s.count = 0
+    a = (CAppend * 3)(*[s.c() for s in app])
+    st = StepStats()
+    rc = lib().qed_step_merged(tables.handle, C.byref(cfg), C.byref(e), a, float(dt), C.c_uint64(seed),
+                               C.c_uint32(step_index), C.byref(st), _stream(stream))
+    for k in range(3):
+        app[k].count = int(a[k].count)
+        main[k].count = int(e.s[k].count)
     if check:
         _check(rc)
     return rc, st

@@ -18,11 +18,11 @@ import time
 import numpy as np
 
 from . import (AppendBuffer, Fields, Store, field_buffers, gather_fields, merge, resample as resample_ensemble,
-               resample_cfg, step, step_cfg)
+               resample_cfg, step, step_cfg, step_merged)
 
 
 def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_capacity, dtype=None, seed: int = 0,
-        cfg=None, on_step=None, stream=None, resample=None, grid=None):
+        cfg=None, on_step=None, stream=None, resample=None, grid=None, merged=True):
     """species: [(p [n, 3], w [n], tau [n], id [n])] or, with positions,
     [(p, w, tau, id, x [n, 3])] for e-, e+, photons;
     field_of_step(k): the [1, 6] field (ex ey ez bx by bz) shared by all
@@ -31,8 +31,10 @@ def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_cap
     wrapped into the box and the grid is interpolated at it (gather_fields);
     resample: None, or the keyword arguments of resample_cfg
     (photon_energy_min, target) applied after every merge, with the cascade's
-    seed and the step index.  Returns (counts [steps + 1, 3], per-step stats,
-    seconds per step, the final device stores, total weight [steps + 1, 3])."""
+    seed and the step index; merged: one qed_step_merged call per step (else
+    qed_step then qed_merge; the results are identical).  Returns (counts
+    [steps + 1, 3], per-step stats, seconds per step, the final device stores,
+    total weight [steps + 1, 3])."""
     import torch
     dtype = dtype or torch.float32
     positions = len(species[0]) > 4
@@ -63,10 +65,14 @@ def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_cap
             f = Fields.from_array(np.asarray(field_of_step(k), dtype=np.float64).reshape(1, 6), dtype)
             fields = [f, f, f]
             t0 = time.perf_counter()
-        rc, st = step(tables, main, fields, app, dt, seed, k, cfg, stream=stream, check=False)
+        if merged:
+            rc, st = step_merged(tables, main, fields, app, dt, seed, k, cfg, stream=stream, check=False)
+        else:
+            rc, st = step(tables, main, fields, app, dt, seed, k, cfg, stream=stream, check=False)
         if rc != 0:
             raise RuntimeError(f"cascade step {k}: status {rc}, required capacity {list(st.required_capacity)}")
-        merge(main, fields, app, stream=stream)
+        if not merged:
+            merge(main, fields, app, stream=stream)
         if resample is not None:
             resample_ensemble(main, fields, resample_cfg(seed=seed, step=k, **resample), stream=stream)
         torch.cuda.synchronize()

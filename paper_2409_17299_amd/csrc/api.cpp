@@ -32,6 +32,7 @@ constexpr int kMergeCount = kSlots + 3;
 constexpr int kAliveCount = kSlots + 4;
 constexpr int kStats = kSlots + 8;      // 8 words
 constexpr int kResampleCount = kSlots + 16;  // 3 words: survivors of each species' compaction
+constexpr int kMergedCursor = kSlots + 24;   // photons in the main arrays so far (qed_step_merged)
 
 // Library-owned scratch of one device: per-particle counts, offsets and event
 // list of the largest launch so far, look-back words, and a control block.
@@ -49,6 +50,9 @@ struct Scratch {
   int num_cu = 0;
   size_t max_lds = 0;
   double* level = nullptr;  // partial sums of the leveling threshold solve
+  uint64_t* state_m = nullptr;  // look-back words of the merged photon count pass, with their own epochs
+  int64_t tiles_m_cap = 0;
+  uint32_t epoch_m = 0;
   std::mutex mu;
 };
 
@@ -116,6 +120,44 @@ uint32_t next_epoch(Scratch* s) {
   s->epoch = (s->epoch + 1) & 0xFFFFFFu;
   if (s->epoch == 0) s->epoch = 1;
   return s->epoch;
+}
+
+uint32_t next_epoch_m(Scratch* s) {
+  s->epoch_m = (s->epoch_m + 1) & 0xFFFFFFu;
+  if (s->epoch_m == 0) s->epoch_m = 1;
+  return s->epoch_m;
+}
+
+// look-back words for `tiles` tiles of the merged photon count pass
+qed_status ensure_merged_state(Scratch* s, int64_t tiles) {
+  if (tiles <= s->tiles_m_cap) return QED_OK;
+  if (s->state_m) {
+    SFQED_HIP(hipDeviceSynchronize());
+    (void)hipFree(s->state_m);
+    s->state_m = nullptr;
+  }
+  SFQED_HIP(hipMalloc(&s->state_m, sizeof(uint64_t) * tiles));
+  SFQED_HIP(hipMemset(s->state_m, 0, sizeof(uint64_t) * tiles));
+  s->tiles_m_cap = tiles;
+  s->epoch_m = 0;
+  return QED_OK;
+}
+
+// look-back words for `tiles` tiles of a merge or resampling compaction
+qed_status ensure_merge_tiles(Scratch* s, int64_t tiles) {
+  if (tiles <= s->tiles_cap) return QED_OK;
+  if (s->state_c) {
+    SFQED_HIP(hipDeviceSynchronize());
+    (void)hipFree(s->state_c);
+    (void)hipFree(s->state_f);
+  }
+  SFQED_HIP(hipMalloc(&s->state_c, sizeof(uint64_t) * tiles));
+  SFQED_HIP(hipMalloc(&s->state_f, sizeof(uint64_t) * tiles));
+  SFQED_HIP(hipMemset(s->state_c, 0, sizeof(uint64_t) * tiles));
+  SFQED_HIP(hipMemset(s->state_f, 0, sizeof(uint64_t) * tiles));
+  s->tiles_cap = tiles;
+  s->epoch = 0;
+  return QED_OK;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -228,7 +270,7 @@ template <typename T>
 qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const qed_step_cfg* cfg,
                       const qed_ensemble* ens, qed_append* app, int species, bool from_main, int64_t begin0,
                       int64_t n0, int64_t begin1, int64_t n1, double dt, uint64_t seed, uint32_t step, int* slot,
-                      bool positions, EventLog& log, qed_step_stats* stats) {
+                      bool positions, EventLog& log, qed_step_stats* stats, bool merged = false) {
   // part 0: species, particles [begin0, begin0 + n0); part 1 (leptons): species + 1, [begin1, begin1 + n1)
   const int64_t n = n0 + n1;
   if (n <= 0) return QED_OK;
@@ -277,6 +319,19 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   a.list_len = reinterpret_cast<int64_t*>(S->ctrl + kListLen);
   a.queue = reinterpret_cast<unsigned long long*>(S->ctrl + *slot);
   a.stats = reinterpret_cast<unsigned long long*>(S->ctrl + kStats);
+  // appended photons with the merge folded in: survivors go to the main photon
+  // arrays (the photon count pass uses no work queue, so its first queue word
+  // serves as the tile counter)
+  const bool fold = merged && photon && !from_main;
+  if (fold) {
+    a.dst = view_of<T>(ens->s[2]);
+    a.dst_cap = ens->s[2].capacity;
+    a.dst_cursor = reinterpret_cast<int64_t*>(S->ctrl + kMergedCursor);
+    if ((rc = ensure_merged_state(S, (n + kMergedTile - 1) / kMergedTile)) != QED_OK) return rc;
+    a.dst_state = S->state_m;
+    a.dst_epoch = next_epoch_m(S);
+    a.dst_ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot);
+  }
   a.dt = dt;
   a.seed = seed;
   a.step = step;
@@ -315,7 +370,9 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
 
   const int k_count = photon ? 3 : 0, k_write = photon ? 4 : 2;
   hipEvent_t e0 = log.begin();
-  hipError_t e = photon ? launch_count<T, true>(a, grid, lds, st) : launch_count<T, false>(a, grid, lds, st);
+  hipError_t e = fold     ? launch_count_photon_merged<T>(a, grid, lds, st)
+                 : photon ? launch_count<T, true>(a, grid, lds, st)
+                          : launch_count<T, false>(a, grid, lds, st);
   if (e != hipSuccess) {
     set_error(std::string("count kernel: ") + hipGetErrorString(e));
     return QED_ERR_HIP;
@@ -348,7 +405,8 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
 
 template <typename T>
 qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble* ens, qed_append* app,
-                     double dt, uint64_t seed, uint32_t step, qed_step_stats* stats, hipStream_t st) {
+                     double dt, uint64_t seed, uint32_t step, qed_step_stats* stats, hipStream_t st,
+                     bool merged = false) {
   Scratch* S = scratch_for_current_device();
   if (!S) {
     set_error("no HIP device");
@@ -382,7 +440,7 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
     if (n0 + n1 <= 0) return QED_OK;
     ++launches;
     return run_launch<T>(S, st, tab, cfg, ens, app, species, from_main, begin0, n0, begin1, n1, dt, seed, step,
-                         &slot, positions, log, &local);
+                         &slot, positions, log, &local, merged);
   };
   // round 0: the input ensemble, then the photons its leptons emitted
   if ((rc = launch(0, true, 0, ens->s[0].count, 0, ens->s[1].count)) != QED_OK) return rc;
@@ -391,6 +449,30 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   bool overflow = cur[0] > capg;
   if (!overflow) {
     if ((rc = launch(2, true, 0, ens->s[2].count, 0, 0)) != QED_OK) return rc;
+    // merged: the input photons are read for the last time in this round, so
+    // their survivors are compacted now; appended survivors follow them
+    if (merged && ens->s[2].count > 0) {
+      const int64_t tiles = (ens->s[2].count + kMergeTile - 1) / kMergeTile;
+      if ((rc = ensure_merge_tiles(S, tiles)) != QED_OK) return rc;
+      if (slot + kLaunchWords > kSlots) {
+        SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t) * kSlots, st));
+        slot = 0;
+      }
+      MergeArgs<T> m;
+      m.main = view_of<T>(ens->s[2]);
+      m.app = nullptr;
+      m.app_pos = nullptr;
+      m.n_main = ens->s[2].count;
+      m.n_app = 0;
+      m.positions = positions ? 1 : 0;
+      m.state = S->state_c;
+      m.epoch = next_epoch(S);
+      m.ticket = reinterpret_cast<unsigned long long*>(S->ctrl + slot);
+      m.num_tiles = tiles;
+      m.out_count = reinterpret_cast<int64_t*>(S->ctrl + kMergedCursor);
+      slot += kLaunchWords;
+      SFQED_HIP(launch_merge_photons<T>(m, st));
+    }
     const int64_t g_hi = cur[0];
     if ((rc = launch(2, false, 0, g_hi, 0, 0)) != QED_OK) return rc;
     g_done = g_hi;
@@ -438,6 +520,26 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   if (overflow) {
     set_error("append capacity exceeded");
     return QED_ERR_CAPACITY;
+  }
+  if (merged) {
+    // the photons are merged; the leptons' records go after the input leptons
+    int64_t photons = 0;
+    SFQED_HIP(hipMemcpyAsync(&photons, S->ctrl + kMergedCursor, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SFQED_HIP(hipStreamSynchronize(st));
+    if (ens->s[0].count + app[0].count > ens->s[0].capacity || ens->s[1].count + app[1].count > ens->s[1].capacity ||
+        photons > ens->s[2].capacity) {
+      ens->s[2].count = std::min(photons, ens->s[2].capacity);
+      set_error("merged step: main capacity exceeded (photons " + std::to_string(photons) + ")");
+      return QED_ERR_CAPACITY;
+    }
+    for (int s = 0; s < 2; ++s)
+      SFQED_HIP(launch_append_records<T>(view_of<T>(ens->s[s]), ens->s[s].count,
+                                         static_cast<const Rec<T>*>(app[s].rec), static_cast<const T*>(app[s].pos),
+                                         app[s].count, positions ? 1 : 0, st));
+    SFQED_HIP(hipStreamSynchronize(st));
+    ens->s[0].count += app[0].count;
+    ens->s[1].count += app[1].count;
+    ens->s[2].count = photons;
   }
   if (dev_stats[kStatCapped]) {
     set_error("a particle reached max_events");
@@ -778,6 +880,30 @@ qed_status qed_step(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (ens->dtype == QED_F32) return step_impl<float>(tab, cfg, ens, app, dt, seed, step, stats, st);
   return step_impl<double>(tab, cfg, ens, app, dt, seed, step, stats, st);
+}
+
+qed_status qed_step_merged(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble* ens, qed_append app[3],
+                           double dt, uint64_t seed, uint32_t step, qed_step_stats* stats, void* stream) {
+  if (!tab || !cfg || !ens || !app) {
+    set_error("null argument");
+    return QED_ERR_ARG;
+  }
+  if (!finite_pos(dt) || (ens->dtype != QED_F32 && ens->dtype != QED_F64) || !(cfg->gamma_min >= 1.0) ||
+      cfg->max_events < 1 || cfg->sampler != QED_SAMPLER_TABLE) {
+    set_error("invalid step configuration");
+    return QED_ERR_ARG;
+  }
+  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
+  for (int s = 0; s < 3; ++s) {
+    if (!species_ok(ens->s[s], s == 2, positions) || !append_ok(app[s], positions) ||
+        !fields_ok(ens->f[s], ens->s[s].count)) {
+      set_error("invalid species " + std::to_string(s));
+      return QED_ERR_ARG;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ens->dtype == QED_F32) return step_impl<float>(tab, cfg, ens, app, dt, seed, step, stats, st, true);
+  return step_impl<double>(tab, cfg, ens, app, dt, seed, step, stats, st, true);
 }
 
 qed_status qed_merge(qed_ensemble* ens, const qed_append app[3], void* stream) {

@@ -12,6 +12,9 @@ namespace sfqed {
 // kernel runs one block per CU.
 constexpr int kStepThreads = 512;
 constexpr int kStepWavesPerSimd = 4;
+// photons merged inside the step: photons per thread and per tile of the count pass
+constexpr int kMergedItems = 4;
+constexpr int kMergedTile = kStepThreads * kMergedItems;
 // lepton work queue: counters per launch and kernel (see wq_take)
 constexpr int kQueueParts = 8;
 constexpr int kQueueStride = 16;  // 64-bit words between counters: one 128-byte line each
@@ -72,6 +75,14 @@ struct StepArgs {
   double gamma_min;
   int64_t max_events;
   TableView tab;
+  // photons merged inside the step (k_count_photon_merged): survivors of an
+  // appended range go straight into the main photon arrays
+  SpeciesView<T> dst;               // the main photons
+  int64_t dst_cap;                  // their capacity (nothing is written at or past it)
+  int64_t* dst_cursor;              // photons in dst so far: read by the first tile, set by the last
+  uint64_t* dst_state;              // look-back words, one per tile of kStepThreads photons
+  uint32_t dst_epoch;
+  unsigned long long* dst_ticket;   // tile counter, zero at launch
 };
 
 struct ScanArgs {
@@ -137,6 +148,8 @@ struct ResampleArgs {
 
 template <typename T, bool kPhoton>
 hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st);
+template <typename T>
+hipError_t launch_count_photon_merged(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st);
 template <typename T, bool kPhoton>
 hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st);
 hipError_t launch_scan(const ScanArgs& s, hipStream_t st);

@@ -714,6 +714,108 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   if (__any(any_event) && lane_id() == 0) atomicMax(&a.stats[kStatMaxEvents], 1ull);
 }
 
+// The photon count pass of an appended range with the merge folded in: tiles
+// of kMergedTile photons (kMergedItems per thread, item-major so that loads of
+// one item are coalesced) are taken in order from a counter; a photon without
+// a pair event survives the step and is written, in its final state, straight
+// into the main photon arrays at dst_cursor + (survivors before it), the place
+// the merge would give it.  A single-pass look-back over tiles gives the
+// offsets; tiles are taken in order, so a block only waits for tiles that
+// running blocks hold.  Photons with events get their counts as in
+// k_count_photon (their pairs are written by k_write_photon).
+template <typename T>
+__global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1)
+    k_count_photon_merged(StepArgs<T> a) {
+  extern __shared__ float lds[];
+  const LdsTables lt = stage_tables<T, true>(a, lds);
+  __shared__ int32_t wsum[kMergedItems][kStepThreads / 64];
+  __shared__ int64_t s_tile, s_base;
+  const int64_t num_tiles = (a.n + kMergedTile - 1) / kMergedTile;
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  int32_t any_event = 0;
+  while (true) {
+    __syncthreads();  // the previous tile's readers of s_tile, s_base and wsum are done
+    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(a.dst_ticket, 1ull);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= num_tiles) break;
+    T p[kMergedItems][3], x[kMergedItems][3];
+    double tau[kMergedItems];
+    float w[kMergedItems];
+    uint64_t id[kMergedItems];
+    uint32_t surv = 0;
+#pragma unroll
+    for (int it = 0; it < kMergedItems; ++it) {
+      const int64_t k = tile * kMergedTile + (int64_t)it * kStepThreads + threadIdx.x;
+      if (k < a.n) {
+        Lane<T> L;
+        load_lane<T>(a, lt.src, k, L);
+        photon_iter<T, false>(a, lt, L, 0);
+        a.counts[k] = L.j;
+        any_event |= L.j;
+        if (L.j == 0) {
+          surv |= 1u << it;
+          for (int c = 0; c < 3; ++c) {
+            p[it][c] = L.p[c];
+            x[it][c] = L.x[c];
+          }
+          tau[it] = L.tau;
+          w[it] = L.w;
+          id[it] = L.id;
+        }
+      }
+    }
+    uint64_t m[kMergedItems];
+#pragma unroll
+    for (int it = 0; it < kMergedItems; ++it) {
+      m[it] = __ballot((surv >> it) & 1u);
+      if (lane == 0) wsum[it][wave] = __popcll(m[it]);
+    }
+    __syncthreads();
+    int32_t pre[kMergedItems];
+    int32_t total = 0;
+#pragma unroll
+    for (int it = 0; it < kMergedItems; ++it) {
+      int32_t before = 0, all = 0;
+      for (int wv = 0; wv < kStepThreads / 64; ++wv) {
+        before += wv < wave ? wsum[it][wv] : 0;
+        all += wsum[it][wv];
+      }
+      pre[it] = total + before + (int32_t)mbcnt(m[it]);
+      total += all;
+    }
+    if (wave == 0) {
+      const int64_t base = (tile == 0 && lane == 0) ? *a.dst_cursor : 0;
+      const int64_t b = lookback(a.dst_state, tile, total, __shfl(base, 0), a.dst_epoch);
+      if (lane == 0) {
+        s_base = b;
+        if (tile == num_tiles - 1) *a.dst_cursor = b + total;
+      }
+    }
+    __syncthreads();
+    const SpeciesView<T>& d = a.dst;
+#pragma unroll
+    for (int it = 0; it < kMergedItems; ++it) {
+      if (!((surv >> it) & 1u)) continue;
+      const int64_t o = s_base + pre[it];
+      if (o >= a.dst_cap) continue;
+      d.px[o] = p[it][0];
+      d.py[o] = p[it][1];
+      d.pz[o] = p[it][2];
+      if (a.positions) {
+        d.x[o] = x[it][0];
+        d.y[o] = x[it][1];
+        d.z[o] = x[it][2];
+      }
+      d.w[o] = w[it];
+      d.tau[o] = tau[it];
+      d.id[o] = id[it];
+      d.alive[o] = 1;
+    }
+  }
+  if (__any(any_event) && lane_id() == 0) atomicMax(&a.stats[kStatMaxEvents], 1ull);
+}
+
 // ------------------------------------------------------------------ scan kernel
 // One tile of kScanTile counts per block: thread t holds items
 // [16 t, 16 t + 16) of the tile (loaded as four 16-byte vectors when the tile
@@ -1307,6 +1409,10 @@ hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t 
   if (a.from_main) return launch_step_kernel(&k_write_lepton<T, true>, a, grid, lds, st);
   return launch_step_kernel(&k_write_lepton<T, false>, a, grid, lds, st);
 }
+template <typename T>
+hipError_t launch_count_photon_merged(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
+  return launch_step_kernel(&k_count_photon_merged<T>, a, grid, lds, st);
+}
 hipError_t launch_scan(const ScanArgs& s, hipStream_t st) {
   hipLaunchKernelGGL(k_scan, dim3((unsigned)s.num_tiles), dim3(kScanThreads), 0, st, s);
   return hipGetLastError();
@@ -1398,6 +1504,8 @@ template hipError_t launch_level_pass<float>(const SpeciesView<float>&, int64_t,
                                                 LevelState*, hipStream_t);
 template hipError_t launch_level_pass<double>(const SpeciesView<double>&, int64_t, int, double, int64_t, int,
                                                  double*, LevelState*, hipStream_t);
+template hipError_t launch_count_photon_merged<float>(const StepArgs<float>&, int, size_t, hipStream_t);
+template hipError_t launch_count_photon_merged<double>(const StepArgs<double>&, int, size_t, hipStream_t);
 template hipError_t launch_resample<float>(const ResampleArgs<float>&, hipStream_t);
 template hipError_t launch_resample<double>(const ResampleArgs<double>&, hipStream_t);
 template hipError_t launch_merge_photons<double>(const MergeArgs<double>&, hipStream_t);

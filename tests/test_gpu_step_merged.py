@@ -1,0 +1,89 @@
+"""qed_step_merged against qed_step followed by qed_merge.
+
+The merged call compacts the input photons after their round and writes each
+appended photon that survives the step straight into the main photon arrays
+(offsets from a single-pass look-back), instead of the merge reading it back
+from its record.  Nothing in the arithmetic changes, so the merged ensemble
+must equal the two-call result exactly: every array, the order and the
+counts, for FP32 and FP64, with and without positions, over several
+generation rounds."""
+import numpy as np
+import pytest
+
+import synth
+
+from gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def build(sf, torch, wl, dtype, x=None, main_extra=(400_000, 400_000, 5_000_000), app_cap=(400_000, 400_000, 5_000_000)):
+    main, fields, app = [], [], []
+    for s, sp in enumerate(wl.species):
+        f = sp.fields if sp.fields.shape[0] else np.zeros((1, 6))
+        main.append(sf.Store.from_arrays(sp.p, sp.w, sp.tau, sp.id, dtype=dtype, photon=s == 2,
+                                         capacity=sp.n + main_extra[s], x=None if x is None else x[s]))
+        fields.append(sf.Fields.from_array(f, dtype))
+        app.append(sf.AppendBuffer(app_cap[s], dtype, positions=x is not None))
+    return main, fields, app
+
+
+def arrays(store):
+    h = store.host()
+    return {k: v for k, v in h.items() if k != "nev"}
+
+
+def compare(sf, torch, wl, dtype, cfg, x=None, steps=1):
+    tabs = sf.Tables()
+    ma, fa, aa = build(sf, torch, wl, dtype, x)
+    mb, fb, ab = build(sf, torch, wl, dtype, x)
+    for k in range(steps):
+        rc, st_a = sf.step(tabs, ma, fa, aa, wl.dt, 5, k, cfg)
+        sf.merge(ma, fa, aa)
+        rc_b, st_b = sf.step_merged(tabs, mb, fb, ab, wl.dt, 5, k, cfg)
+        torch.cuda.synchronize()
+        assert rc == 0 and rc_b == 0
+        assert st_a.n_emit == st_b.n_emit and st_a.n_pair == st_b.n_pair and st_a.n_rounds == st_b.n_rounds
+        for s in range(3):
+            assert ma[s].count == mb[s].count, (k, s, ma[s].count, mb[s].count)
+            A, B = arrays(ma[s]), arrays(mb[s])
+            for name in A:
+                assert np.array_equal(A[name], B[name]), (k, s, name)
+        for s in range(2):
+            assert aa[s].count == ab[s].count
+            assert np.array_equal(aa[s].records(), ab[s].records())
+    return st_a, [m.count for m in ma]
+
+
+@pytest.mark.parametrize("dtype_name", ["float32", "float64"])
+def test_crossed_field_sample(dtype_name):
+    torch, sf = need_gpu()
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 200), np.arange(0, 4_000_000, 200),
+                                                  np.arange(0, 2_000_000, 200)])
+    st, counts = compare(sf, torch, wl, getattr(torch, dtype_name), sf.step_cfg(push=False, gamma_min=2.0))
+    print(f"{dtype_name}: {st.n_emit} photons, {st.n_pair} pairs, {st.n_rounds} rounds; merged counts {counts}")
+    assert st.n_pair > 1000 and st.n_rounds >= 5
+
+
+def test_positions_and_cascade_steps():
+    """Positions on, push on, three consecutive steps of the rotating-field
+    cascade (the merged ensemble feeds the next step)."""
+    torch, sf = need_gpu()
+    wl = synth.rotating_e(1_000_000, indices=np.arange(0, 1_000_000, 500))
+    rng = np.random.default_rng(8)
+    x = [rng.normal(0.0, 1e3, (sp.n, 3)) for sp in wl.species]
+    st, counts = compare(sf, torch, wl, torch.float32, sf.step_cfg(push=True), x=x, steps=3)
+    print(f"3 steps: merged counts {counts}")
+    assert counts[2] > 0 and counts[0] > wl.species[0].n
+
+
+def test_photon_capacity():
+    torch, sf = need_gpu()
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 2000), np.arange(0, 4_000_000, 2000),
+                                                  np.arange(0, 2_000_000, 2000)])
+    main, fields, app = build(sf, torch, wl, torch.float32, main_extra=(100_000, 100_000, 10))
+    rc, st = sf.step_merged(sf.Tables(), main, fields, app, wl.dt, 0, 0, sf.step_cfg(push=False, gamma_min=2.0),
+                            check=False)
+    torch.cuda.synchronize()
+    assert rc == 2
+    assert main[2].count <= main[2].capacity
