@@ -33,9 +33,12 @@ def log(*a):
 
 
 # ----------------------------------------------------------------------------- algorithmic bytes
-def kernel_bytes(name: str, st: dict, n_main: list, n_step: int) -> float:
+def kernel_bytes(name: str, st: dict, n_main: list, n_step: int, merged: bool = True) -> float:
     """Bytes the method must move in all launches of one kernel during n_step steps
-    (FP32 momenta/fields/times, FP64 optical depth, u64 ids; push off, no positions)."""
+    (FP32 momenta/fields/times, FP64 optical depth, u64 ids; push off, no positions).
+    merged: the photon count pass also writes each surviving photon into the
+    main arrays (p 12, w 4, tau 8, id 8, alive 1) instead of its tau; the
+    2e6 input photons, which only write tau, are counted the same way (0.3%)."""
     P = st["kernel_particles"]
     ev_l, ev_p = st["event_particles"]
     n_emit, n_pair = st["n_emit"], st["n_pair"]
@@ -55,7 +58,7 @@ def kernel_bytes(name: str, st: dict, n_main: list, n_step: int) -> float:
         return ev_l * (52 + 4 + 8 + 4 + 12 + 8) + n_emit * 48
     if name == "count_photon":
         n = P[3]
-        return n * (52 + 4) + (n - main_p) * 8 + (n - ev_p) * 8
+        return n * (52 + 4) + (n - main_p) * 8 + (n - ev_p) * (33 if merged else 8)
     if name == "write_photon":
         return ev_p * (52 + 4 + 8 + 4 + 1) + 2 * n_pair * 48
     raise KeyError(name)
@@ -540,7 +543,7 @@ def main(argv=None):
     for k, name in enumerate(sf.StepStats.KERNELS):
         if S["kernel_launches"][k] == 0:
             continue
-        b = kernel_bytes(name, S, dw.n, args.steps)
+        b = kernel_bytes(name, S, dw.n, args.steps, merged=not args.two_call)
         kern[name] = {"ms_total": S["kernel_ms"][k], "launches": S["kernel_launches"][k],
                       "avg_launch_ms": S["kernel_ms"][k] / S["kernel_launches"][k],
                       "bytes": b, "gbs": b / (S["kernel_ms"][k] * 1e-3) / 1e9}
