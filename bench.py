@@ -242,7 +242,7 @@ def cpu_simd_baseline(full_n, stride, gamma_min, steps=3):
 
 
 # ----------------------------------------------------------------------------- rotating-field cascade
-def cascade_bench(sf, torch, steps: int, n_seeds: int) -> dict:
+def cascade_bench(sf, torch, steps: int, n_seeds: int, merged: bool = True) -> dict:
     """20 global steps of the rotating-field cascade from n_seeds electrons
     (FP32, push on), qed_step + qed_merge each step; the ensemble grows ~200x."""
     import numpy as np
@@ -260,7 +260,7 @@ def cascade_bench(sf, torch, steps: int, n_seeds: int) -> dict:
         log(f"  step {k}: counts {c}, {st.n_emit} photons, {st.n_pair} pairs, {st.n_rounds} rounds, {sec * 1e3:.1f} ms")
 
     counts, stats, secs, _, _ = cascade.run(tables, sp, wl.dt, steps, lambda k: synth.rotating_field(e0, wdt, k), cap,
-                                         app, dtype=torch.float32, seed=0, on_step=report)
+                                         app, dtype=torch.float32, seed=0, on_step=report, merged=merged)
     particle_steps = float(counts[:-1].sum())
     events = float(sum(st.n_emit + st.n_pair for st in stats))
     t = float(sum(secs))
@@ -277,7 +277,7 @@ def cascade_bench(sf, torch, steps: int, n_seeds: int) -> dict:
 
 
 # ----------------------------------------------------------------------------- standing-wave test problem
-def standing_wave_bench(sf, torch, steps: int, n_seeds: int, target: int, e_min: float) -> dict:
+def standing_wave_bench(sf, torch, steps: int, n_seeds: int, target: int, e_min: float, merged: bool = True) -> dict:
     """The test problem of Sec. 5.1 on its grid: n_seeds e-/e+ at rest in a
     periodic cube of one wavelength, the standing circularly polarised wave
     filled on the device each step, positions wrapped and fields gathered,
@@ -304,7 +304,7 @@ def standing_wave_bench(sf, torch, steps: int, n_seeds: int, target: int, e_min:
                 f"{sec * 1e3:.2f} ms")
 
     counts, stats, secs, main, weights = cascade.run(tables, sp, wl.dt, steps, None, cap, app, dtype=dtype, seed=0,
-                                                     on_step=report, grid=grid,
+                                                     on_step=report, grid=grid, merged=merged,
                                                      resample=dict(photon_energy_min=e_min, target=targets))
     particle_steps = float(counts[:-1].sum())
     events = float(sum(st.n_emit + st.n_pair for st in stats))
@@ -474,11 +474,11 @@ def main(argv=None):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.workload == "rotating_e":
-        print(json.dumps(cascade_bench(sf, torch, 20, args.seeds)), flush=True)
+        print(json.dumps(cascade_bench(sf, torch, 20, args.seeds, merged=not args.two_call)), flush=True)
         return 0
     if args.workload == "standing_wave":
-        print(json.dumps(standing_wave_bench(sf, torch, args.sw_steps, args.sw_seeds, args.sw_target, 2.0)),
-              flush=True)
+        print(json.dumps(standing_wave_bench(sf, torch, args.sw_steps, args.sw_seeds, args.sw_target, 2.0,
+                                             merged=not args.two_call)), flush=True)
         return 0
     if args.workload == "static_b_sweep":
         print(json.dumps(precision_sweep(sf, torch, 200_000_000, 10_000_000)), flush=True)
