@@ -331,6 +331,7 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
     a.dst_state = S->state_m;
     a.dst_epoch = next_epoch_m(S);
     a.dst_ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot);
+    a.pair_cursor = reinterpret_cast<int64_t*>(S->ctrl + kCurLepton);
   }
   a.dt = dt;
   a.seed = seed;
@@ -378,13 +379,15 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
     return QED_ERR_HIP;
   }
   log.end(k_count, e0);
-  e0 = log.begin();
-  e = launch_scan(s, st);
-  if (e != hipSuccess) {
-    set_error(std::string("scan kernel: ") + hipGetErrorString(e));
-    return QED_ERR_HIP;
+  if (!fold) {  // the merged photon pass writes its event list itself
+    e0 = log.begin();
+    e = launch_scan(s, st);
+    if (e != hipSuccess) {
+      set_error(std::string("scan kernel: ") + hipGetErrorString(e));
+      return QED_ERR_HIP;
+    }
+    log.end(1, e0);
   }
-  log.end(1, e0);
   e0 = log.begin();
   // The lepton write kernel runs one block per CU (two waves per SIMD): it is
   // bound by the memory side of its scattered child stores, and half the
@@ -397,6 +400,7 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   }
   log.end(k_write, e0);
   for (int k : {k_count, 1, k_write}) {
+    if (k == 1 && fold) continue;
     stats->kernel_launches[k] += 1;
     stats->kernel_particles[k] += n;
   }

@@ -83,6 +83,7 @@ struct StepArgs {
   uint64_t* dst_state;              // look-back words, one per tile of kStepThreads photons
   uint32_t dst_epoch;
   unsigned long long* dst_ticket;   // tile counter, zero at launch
+  int64_t* pair_cursor;             // pairs appended so far (the scan's cursor of a photon launch)
 };
 
 struct ScanArgs {

@@ -716,13 +716,19 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
 
 // The photon count pass of an appended range with the merge folded in: tiles
 // of kMergedTile photons (kMergedItems per thread, item-major so that loads of
-// one item are coalesced) are taken in order from a counter; a photon without
+// one item are coalesced) are taken in order from a counter.  A photon without
 // a pair event survives the step and is written, in its final state, straight
-// into the main photon arrays at dst_cursor + (survivors before it), the place
-// the merge would give it.  A single-pass look-back over tiles gives the
-// offsets; tiles are taken in order, so a block only waits for tiles that
-// running blocks hold.  Photons with events get their counts as in
-// k_count_photon (their pairs are written by k_write_photon).
+// into the main photon arrays at (photons there before the launch) +
+// (survivors before it), the place the merge would give it.  A photon has at
+// most one event, so the same count also places the others: a photon with an
+// event is the (k - survivors before k)-th event of the launch, and its pair
+// goes to the lepton buffers at the pair cursor plus that index.  This pass
+// therefore writes the event list and first-child offsets itself (no counts,
+// no scan).  A single-pass look-back over tiles gives the survivors before each
+// tile; tiles are taken in order, so a block only waits for tiles that running
+// blocks hold.  Every block reads the two cursors before it takes its first
+// tile: the last tile, which moves them, cannot finish before every earlier
+// tile has published, and a block that has not taken a tile holds one of them.
 template <typename T>
 __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1)
     k_count_photon_merged(StepArgs<T> a) {
@@ -732,6 +738,7 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   __shared__ int64_t s_tile, s_base;
   const int64_t num_tiles = (a.n + kMergedTile - 1) / kMergedTile;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t dst0 = *a.dst_cursor, pair0 = *a.pair_cursor;
   int32_t any_event = 0;
   while (true) {
     __syncthreads();  // the previous tile's readers of s_tile, s_base and wsum are done
@@ -743,7 +750,7 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
     double tau[kMergedItems];
     float w[kMergedItems];
     uint64_t id[kMergedItems];
-    uint32_t surv = 0;
+    uint32_t surv = 0, event = 0;
 #pragma unroll
     for (int it = 0; it < kMergedItems; ++it) {
       const int64_t k = tile * kMergedTile + (int64_t)it * kStepThreads + threadIdx.x;
@@ -751,8 +758,8 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
         Lane<T> L;
         load_lane<T>(a, lt.src, k, L);
         photon_iter<T, false>(a, lt, L, 0);
-        a.counts[k] = L.j;
         any_event |= L.j;
+        event |= (L.j != 0 ? 1u : 0u) << it;
         if (L.j == 0) {
           surv |= 1u << it;
           for (int c = 0; c < 3; ++c) {
@@ -784,20 +791,31 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
       pre[it] = total + before + (int32_t)mbcnt(m[it]);
       total += all;
     }
-    if (wave == 0) {
-      const int64_t base = (tile == 0 && lane == 0) ? *a.dst_cursor : 0;
-      const int64_t b = lookback(a.dst_state, tile, total, __shfl(base, 0), a.dst_epoch);
+    if (wave == 0) {  // survivors of this launch before the tile
+      const int64_t b = lookback(a.dst_state, tile, total, 0, a.dst_epoch);
       if (lane == 0) {
         s_base = b;
-        if (tile == num_tiles - 1) *a.dst_cursor = b + total;
+        if (tile == num_tiles - 1) {
+          const int64_t events = a.n - (b + total);
+          *a.dst_cursor = dst0 + b + total;
+          *a.pair_cursor = pair0 + events;
+          *const_cast<int64_t*>(a.list_len) = events;  // a control word the scan writes in other launches
+          atomicAdd(&a.stats[kStatEventParticles + 1], (unsigned long long)events);
+        }
       }
     }
     __syncthreads();
     const SpeciesView<T>& d = a.dst;
 #pragma unroll
     for (int it = 0; it < kMergedItems; ++it) {
+      if ((event >> it) & 1u) {  // the e-th event of the launch, e = k - survivors before k
+        const int64_t k = tile * kMergedTile + (int64_t)it * kStepThreads + threadIdx.x;
+        const int64_t e = k - (s_base + pre[it]);
+        a.list[e] = (int32_t)k;
+        a.offsets[e] = pair0 + e;
+      }
       if (!((surv >> it) & 1u)) continue;
-      const int64_t o = s_base + pre[it];
+      const int64_t o = dst0 + s_base + pre[it];
       if (o >= a.dst_cap) continue;
       d.px[o] = p[it][0];
       d.py[o] = p[it][1];
