@@ -36,9 +36,11 @@ def log(*a):
 def kernel_bytes(name: str, st: dict, n_main: list, n_step: int, merged: bool = True) -> float:
     """Bytes the method must move in all launches of one kernel during n_step steps
     (FP32 momenta/fields/times, FP64 optical depth, u64 ids; push off, no positions).
-    merged: the photon count pass also writes each surviving photon into the
-    main arrays (p 12, w 4, tau 8, id 8, alive 1) instead of its tau; the
-    2e6 input photons, which only write tau, are counted the same way (0.3%)."""
+    merged: the photon count pass of appended photons writes each survivor into
+    the main arrays (p 12, w 4, tau 8, id 8, alive 1) instead of its tau and
+    count, and the event list (index 4, offset 8) of the others, so the scan
+    runs over lepton launches only; the 2e6 input photons, which take the
+    plain passes, are counted the same way (0.3%)."""
     P = st["kernel_particles"]
     ev_l, ev_p = st["event_particles"]
     n_emit, n_pair = st["n_emit"], st["n_pair"]
@@ -51,14 +53,16 @@ def kernel_bytes(name: str, st: dict, n_main: list, n_step: int, merged: bool = 
         return n * (52 + 4) + (n - main_l) * 8 + (n - ev_l) * 8
     if name == "scan":
         # read every count; write index and first-child offset of each particle with events
-        return P[1] * 4 + (ev_l + ev_p) * (4 + 8)
+        return P[1] * 4 + (ev_l + (0 if merged else ev_p)) * (4 + 8)
     if name == "write_lepton":
         # per particle with events: state 52 + w 4 (+ root/t_birth) + offset 8 + list 4, final p 12 + tau 8;
         # per child: one 48-byte record
         return ev_l * (52 + 4 + 8 + 4 + 12 + 8) + n_emit * 48
     if name == "count_photon":
         n = P[3]
-        return n * (52 + 4) + (n - main_p) * 8 + (n - ev_p) * (33 if merged else 8)
+        if merged:
+            return n * 52 + (n - main_p) * 8 + (n - ev_p) * 33 + ev_p * 12
+        return n * (52 + 4) + (n - main_p) * 8 + (n - ev_p) * 8
     if name == "write_photon":
         return ev_p * (52 + 4 + 8 + 4 + 1) + 2 * n_pair * 48
     raise KeyError(name)
