@@ -16,8 +16,16 @@
  * Memory: every particle and field array is a device pointer owned by the
  * caller (for example torch tensors); tables and surrogate networks are owned
  * by the library.  All calls are ordered on the HIP stream passed as
- * `stream` (NULL = the null stream).  qed_step synchronises that stream once
- * per generation round to read the append counters; no other call blocks.
+ * `stream` (NULL = the null stream).  Calls that read counts back wait for
+ * that stream: qed_step and qed_step_merged once per generation round (the
+ * append counters), qed_merge and qed_resample at their end (the new counts),
+ * qed_build_rate_tables and qed_mlp_set_params / qed_mlp_get_params once.
+ * The others only queue work.
+ *
+ * Concurrency: the library keeps one set of counters and look-back words per
+ * device and reuses it in every call on that device.  Calls on one device must
+ * therefore not overlap on the GPU: issue them on one stream, or synchronise
+ * before switching streams.
  *
  * Errors: every function returns a qed_status and never aborts.  Invalid
  * arguments are rejected before any work is queued.

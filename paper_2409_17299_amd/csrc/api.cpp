@@ -116,15 +116,30 @@ qed_status ensure_scratch(Scratch* s, int64_t n) {
   return QED_OK;
 }
 
-uint32_t next_epoch(Scratch* s) {
+// A look-back word carries the 24-bit epoch of the launch that wrote it, so a
+// launch never reads a word left by an earlier one as its own.  When the
+// counter wraps, words written 2^24 - 1 launches earlier would match again:
+// they are cleared on the stream, ahead of the launch, before epoch 1 is
+// reused.  Returns 0 (never a valid epoch) if the clear cannot be queued.
+uint32_t next_epoch(Scratch* s, hipStream_t st) {
   s->epoch = (s->epoch + 1) & 0xFFFFFFu;
-  if (s->epoch == 0) s->epoch = 1;
+  if (s->epoch == 0) {
+    s->epoch = 1;
+    const size_t bytes = sizeof(uint64_t) * (size_t)s->tiles_cap;
+    if (bytes && (hipMemsetAsync(s->state_c, 0, bytes, st) != hipSuccess ||
+                  hipMemsetAsync(s->state_f, 0, bytes, st) != hipSuccess))
+      return 0;
+  }
   return s->epoch;
 }
 
-uint32_t next_epoch_m(Scratch* s) {
+uint32_t next_epoch_m(Scratch* s, hipStream_t st) {
   s->epoch_m = (s->epoch_m + 1) & 0xFFFFFFu;
-  if (s->epoch_m == 0) s->epoch_m = 1;
+  if (s->epoch_m == 0) {
+    s->epoch_m = 1;
+    const size_t bytes = sizeof(uint64_t) * (size_t)s->tiles_m_cap;
+    if (bytes && hipMemsetAsync(s->state_m, 0, bytes, st) != hipSuccess) return 0;
+  }
   return s->epoch_m;
 }
 
@@ -329,7 +344,11 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
     a.dst_cursor = reinterpret_cast<int64_t*>(S->ctrl + kMergedCursor);
     if ((rc = ensure_merged_state(S, (n + kMergedTile - 1) / kMergedTile)) != QED_OK) return rc;
     a.dst_state = S->state_m;
-    a.dst_epoch = next_epoch_m(S);
+    a.dst_epoch = next_epoch_m(S, st);
+    if (!a.dst_epoch) {
+      set_error("clearing the look-back words failed");
+      return QED_ERR_HIP;
+    }
     a.dst_ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot);
     a.pair_cursor = reinterpret_cast<int64_t*>(S->ctrl + kCurLepton);
   }
@@ -363,7 +382,11 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   s.list_len = reinterpret_cast<int64_t*>(S->ctrl + kListLen);
   s.state_c = S->state_c;
   s.state_f = S->state_f;
-  s.epoch = next_epoch(S);
+  s.epoch = next_epoch(S, st);
+  if (!s.epoch) {
+    set_error("clearing the look-back words failed");
+    return QED_ERR_HIP;
+  }
   s.ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot + 2 * kQueueWords);
   s.num_tiles = (n + kScanTile - 1) / kScanTile;
   s.event_particles = reinterpret_cast<unsigned long long*>(S->ctrl + kStats + kStatEventParticles + p);
@@ -470,7 +493,11 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
       m.n_app = 0;
       m.positions = positions ? 1 : 0;
       m.state = S->state_c;
-      m.epoch = next_epoch(S);
+      m.epoch = next_epoch(S, st);
+      if (!m.epoch) {
+        set_error("clearing the look-back words failed");
+        return QED_ERR_HIP;
+      }
       m.ticket = reinterpret_cast<unsigned long long*>(S->ctrl + slot);
       m.num_tiles = tiles;
       m.out_count = reinterpret_cast<int64_t*>(S->ctrl + kMergedCursor);
@@ -609,7 +636,11 @@ qed_status merge_impl(qed_ensemble* ens, const qed_append* app, hipStream_t st) 
     m.n_app = app[2].count;
     m.positions = positions ? 1 : 0;
     m.state = S->state_c;
-    m.epoch = next_epoch(S);
+    m.epoch = next_epoch(S, st);
+    if (!m.epoch) {
+      set_error("clearing the look-back words failed");
+      return QED_ERR_HIP;
+    }
     m.ticket = reinterpret_cast<unsigned long long*>(S->ctrl);
     m.num_tiles = tiles;
     m.out_count = reinterpret_cast<int64_t*>(S->ctrl + kMergeCount);
@@ -711,7 +742,11 @@ qed_status resample_impl(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_res
     a.seed = cfg->seed;
     a.step = cfg->step;
     a.state = S->state_c;
-    a.epoch = next_epoch(S);
+    a.epoch = next_epoch(S, st);
+    if (!a.epoch) {
+      set_error("clearing the look-back words failed");
+      return QED_ERR_HIP;
+    }
     a.ticket = reinterpret_cast<unsigned long long*>(S->ctrl);
     a.num_tiles = tiles;
     a.out_count = reinterpret_cast<int64_t*>(S->ctrl + kResampleCount + k);
