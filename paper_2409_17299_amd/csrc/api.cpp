@@ -50,6 +50,10 @@ struct Scratch {
   int num_cu = 0;
   size_t max_lds = 0;
   double* level = nullptr;  // partial sums of the leveling threshold solve
+  // Newton passes queued per species in the next leveling solve: the last
+  // solve's count plus one (the solve usually needs the same number from one
+  // step to the next), at most kLevelDevicePasses
+  int level_passes[3] = {kLevelDevicePasses, kLevelDevicePasses, kLevelDevicePasses};
   uint64_t* state_m = nullptr;  // look-back words of the merged photon count pass, with their own epochs
   int64_t tiles_m_cap = 0;
   uint32_t epoch_m = 0;
@@ -688,7 +692,7 @@ qed_status resample_impl(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_res
     solve[k] = n > 0 && (filter || cfg->target[k] > 0);
     if (!solve[k]) continue;
     const SpeciesView<T> v = view_of<T>(ens->s[k]);
-    const int passes = cfg->target[k] > 0 ? 1 + kLevelDevicePasses : 1;
+    const int passes = cfg->target[k] > 0 ? 1 + S->level_passes[k] : 1;
     for (int q = 0; q < passes; ++q)
       SFQED_HIP(launch_level_pass<T>(v, n, k == 2 ? 1 : 0, e_min2, cfg->target[k], q == 0 ? 1 : 0,
                                      S->level + k * part_words, dstate + k, st));
@@ -705,6 +709,7 @@ qed_status resample_impl(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_res
       SFQED_HIP(hipMemcpyAsync(&ls[k], dstate + k, sizeof(LevelState), hipMemcpyDeviceToHost, st));
       SFQED_HIP(hipStreamSynchronize(st));
     }
+    if (cfg->target[k] > 0) S->level_passes[k] = std::max(2, std::min(kLevelDevicePasses, ls[k].iterations + 1));
   }
   bool compacted[3] = {false, false, false};
   for (int k = 0; k < 3; ++k) {

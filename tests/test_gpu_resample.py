@@ -122,3 +122,26 @@ def test_edge_cases():
     with pytest.raises(sf.SfqedError):
         sf.resample(main, [sf.Fields.from_array(np.zeros((1, 6)), torch.float32)] * 3,
                     sf.resample_cfg(photon_energy_min=-1.0))
+
+
+def test_queued_passes_follow_the_last_solve():
+    """The Newton passes queued without waiting for the host follow the last
+    solve's count (plus one).  A solve that needs more finishes pass by pass on
+    the host and must give the same threshold and survivors as one that had
+    enough passes queued."""
+    torch, sf = need_gpu()
+    # equal weights: w_0 = total / target is already the root, one pass confirms it
+    flat = [(p, np.full_like(w, 0.75), tau, ids, x) for (p, w, tau, ids, x) in ensemble((4000, 4000, 4000), 14)]
+    _, st0 = run(torch, sf, flat, torch.float32, dict(target=(1000, 1000, 1000), seed=3, step=1))
+    assert list(st0.iterations) == [1, 1, 1]
+    data = ensemble((70001, 5003, 123457), 11)
+    cfg = dict(photon_energy_min=2.0, target=(20000, 6000, 40000), seed=7, step=3)
+    main, st = run(torch, sf, data, torch.float32, cfg)   # two passes queued: the host finishes the solve
+    assert st.iterations[0] > 2 and st.iterations[2] > 2
+    for s in range(3):
+        check_species(sf, main[s], data[s], s, st, cfg, np.float32)
+    main2, st2 = run(torch, sf, data, torch.float32, cfg)  # now enough passes are queued
+    assert list(st2.iterations) == list(st.iterations) and list(st2.w_threshold) == list(st.w_threshold)
+    for s in range(3):
+        a, b = main[s].host(), main2[s].host()
+        assert all(np.array_equal(a[k], b[k]) for k in a)
