@@ -416,11 +416,18 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
     log.end(1, e0);
   }
   e0 = log.begin();
-  // The lepton write kernel runs one block per CU (two waves per SIMD): it is
-  // bound by the memory side of its scattered child stores, and half the
-  // waves in flight write as fast.
-  const int wgrid = photon ? grid : (int)std::min<int64_t>((n + kStepThreads - 1) / kStepThreads, S->num_cu);
-  e = photon ? launch_write<T, true>(a, wgrid, lds, st) : launch_write<T, false>(a, wgrid, lds, st);
+  // The lepton write kernel runs one block per CU.  In FP32 that block has
+  // kWriteThreads threads (four waves per SIMD on one copy of the LDS tables)
+  // and stages its child records in LDS, written out in half lines, when the
+  // slots fit beside the tables.  Otherwise (FP64, or tables too large) it
+  // runs kStepThreads threads and stores each record piece by piece.
+  const size_t stage_off = line_stage_offset(sizeof(SrcTable), sizeof(T) == 4, tab->view.rate[0].n,
+                                             tab->view.cdf[0].rows32 * tab->view.cdf[0].cols32);
+  const bool stage = !photon && sizeof(T) == 4 && stage_off + kLineStageBytes + kWriteThreads <= kMaxLdsBytes;
+  const int wthreads = stage ? kWriteThreads : kStepThreads;
+  const int wgrid = photon ? grid : (int)std::min<int64_t>((n + wthreads - 1) / wthreads, S->num_cu);
+  e = photon ? launch_write<T, true>(a, wgrid, lds, st)
+             : launch_write<T, false>(a, wgrid, stage ? stage_off + kLineStageBytes : lds, st, stage);
   if (e != hipSuccess) {
     set_error(std::string("write kernel: ") + hipGetErrorString(e));
     return QED_ERR_HIP;

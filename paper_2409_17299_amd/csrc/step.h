@@ -9,7 +9,7 @@ namespace sfqed {
 // ~78 KiB of LDS per block), so four waves per SIMD; the FP32 count kernels
 // are held to the register budget of that occupancy (the FP64 ones keep their
 // tables in HBM and are limited by registers instead).  The lepton write
-// kernel runs one block per CU.
+// kernel runs one block per CU (see kWriteThreads).
 constexpr int kStepThreads = 512;
 constexpr int kStepWavesPerSimd = 4;
 // photons merged inside the step: photons per thread and per tile of the count pass
@@ -20,6 +20,23 @@ constexpr int kQueueParts = 8;
 constexpr int kQueueStride = 16;  // 64-bit words between counters: one 128-byte line each
 constexpr int kQueueWords = kQueueParts * kQueueStride;
 constexpr uint64_t kChunkMin = 256, kChunkMax = 8192;
+// The lepton write kernel runs one block of kWriteThreads per CU (four waves
+// per SIMD, one copy of the LDS tables).  Its child records are staged per
+// lane in LDS, kLinePieces 16-byte pieces (a 64-byte half line) at a time, and
+// written by kLinePieces lanes per half line: a store instruction then covers
+// 16 half lines instead of 64 scattered pieces.  A lane's slot has one spare
+// piece so that neighbouring slots start in different banks.
+constexpr int kWriteThreads = 1024;
+constexpr int kLinePieces = 4;
+constexpr int kLineShift = 2;  // log2(kLinePieces)
+constexpr int kLineSlot = kLinePieces + 1;
+constexpr size_t kLineStageBytes = (size_t)kWriteThreads * kLineSlot * 16;
+constexpr size_t kMaxLdsBytes = 163840;  // LDS per work-group on gfx950
+// byte offset of the line slots in the write kernel's dynamic LDS: after the
+// source table and, for FP32, the staged rate and CDF tables
+__host__ __device__ constexpr size_t line_stage_offset(size_t src_bytes, int fp32, int rate_n, int cdf_n) {
+  return (src_bytes + (fp32 ? 8 * (size_t)rate_n + 4 * (size_t)cdf_n : 0) + 15) / 16 * 16;
+}
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
@@ -152,7 +169,7 @@ hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t 
 template <typename T>
 hipError_t launch_count_photon_merged(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st);
 template <typename T, bool kPhoton>
-hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st);
+hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st, bool stage = false);
 hipError_t launch_scan(const ScanArgs& s, hipStream_t st);
 template <typename T>
 hipError_t launch_merge_photons(const MergeArgs<T>& a, hipStream_t st);

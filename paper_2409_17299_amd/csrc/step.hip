@@ -934,17 +934,117 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
 }
 
 // ------------------------------------------------------------------ write kernels
-template <typename T, bool kMain>
-__global__ void __launch_bounds__(kStepThreads) k_write_lepton(StepArgs<T> a) {
+// The half line a lane is filling with its parent's child records: global
+// 16-byte piece p goes to slot p mod kLinePieces of half line p / kLinePieces.
+// A record that runs past the end of the half line keeps its tail pieces in
+// registers until the half line has been written.
+template <typename T>
+struct ChildLine {
+  static constexpr int kPieces = (int)(sizeof(Rec<T>) / 16);
+  static_assert(kPieces <= kLinePieces, "a record spans at most two half lines");
+  uint64_t ln;      // global half-line index (address / 64), kNoLine when empty
+  uint32_t mask;    // pieces of the half line that hold data
+  int32_t first;    // first piece of the record held in `ov` (kPieces: none)
+  bool eol;         // the last record reached the end of the half line: write it out
+  uint4 ov[kPieces];
+};
+constexpr uint64_t kNoLine = ~0ull;
+
+template <typename T>
+__device__ __forceinline__ void line_put(uint4* slot, ChildLine<T>& cl, const Rec<T>* base, int64_t o,
+                                         const Rec<T>& r) {
+  constexpr int kP = ChildLine<T>::kPieces;
+  const RecBits<T> b = rec_pack<T>(r);
+  const uint64_t p0 = reinterpret_cast<uint64_t>(base + o) >> 4;
+  const int q0 = (int)(p0 & (kLinePieces - 1));
+  // Records of one parent are contiguous and a half line is written out as
+  // soon as a record reaches its end, so p0 lies in half line ln whenever ln
+  // is set.  (A parent's first half line can start in the middle, so a full
+  // mask is not the test.)
+  if (cl.ln == kNoLine) cl.ln = p0 >> kLineShift;
+  cl.first = kP;
+  cl.eol = q0 + kP >= kLinePieces;
+#pragma unroll
+  for (int k = 0; k < kP; ++k) {
+    if (q0 + k < kLinePieces) {
+      slot[q0 + k] = b.c[k];
+      cl.mask |= 1u << (q0 + k);
+    } else {
+      cl.ov[k] = b.c[k];
+      if (cl.first == kP) cl.first = k;
+    }
+  }
+}
+
+// Writes the half line of every lane whose last record reached the end of it
+// (running past it or not) or whose parent finished (fin), kLinePieces lanes
+// per half line.  Called by the whole wave.
+template <typename T>
+__device__ __forceinline__ void line_flush(uint4* wave_slots, uint8_t* owners, ChildLine<T>& cl, bool fin) {
+  constexpr int kP = ChildLine<T>::kPieces;
+  constexpr uint32_t kPerRound = 64 / kLinePieces;
+  const int lane = lane_id();
+  bool ready = cl.ln != kNoLine && (fin || cl.eol);
+  uint64_t rm = __ballot(ready);
+  while (rm) {
+    const uint32_t r = (uint32_t)__popcll(rm);
+    if (ready) owners[mbcnt(rm)] = (uint8_t)lane;
+    for (uint32_t g0 = 0; g0 < r; g0 += kPerRound) {
+      const uint32_t g = g0 + (uint32_t)(lane >> kLineShift);
+      const int owner = g < r ? (int)owners[g] : lane;
+      const uint64_t oln = __shfl(cl.ln, owner);
+      const uint32_t om = __shfl(cl.mask, owner);
+      const int piece = lane & (kLinePieces - 1);
+      if (g < r && ((om >> piece) & 1u))
+        gptr<uint4>(oln << (kLineShift + 4))[piece] = wave_slots[owner * kLineSlot + piece];
+    }
+    if (ready) {
+      cl.mask = 0;
+      cl.eol = false;
+      if (cl.first < kP) {  // the record's tail starts the next half line
+        cl.ln += 1;
+        uint4* slot = wave_slots + lane * kLineSlot;
+#pragma unroll
+        for (int k = 0; k < kP; ++k)
+          if (k >= cl.first) {
+            slot[k - cl.first] = cl.ov[k];
+            cl.mask |= 1u << (k - cl.first);
+          }
+        cl.first = kP;
+        ready = fin;
+      } else {
+        cl.ln = kNoLine;
+        ready = false;
+      }
+    }
+    rm = __ballot(ready);
+  }
+}
+
+template <typename T, bool kMain, bool kStage>
+__global__ void __launch_bounds__(kStage ? kWriteThreads : kStepThreads) k_write_lepton(StepArgs<T> a) {
+  constexpr int kThreads = kStage ? kWriteThreads : kStepThreads;
   extern __shared__ float lds[];
+  __shared__ uint8_t owners[kStage ? kThreads / 64 : 1][64];
   const LdsTables lt = stage_tables<T, false>(a, lds);
+  uint4* wave_slots = nullptr;
+  if constexpr (kStage) {
+    const size_t off = line_stage_offset(sizeof(SrcTable), sizeof(T) == 4, a.tab.rate[0].n,
+                                         a.tab.cdf[0].rows32 * a.tab.cdf[0].cols32);
+    wave_slots = reinterpret_cast<uint4*>(reinterpret_cast<char*>(lds) + off) + (threadIdx.x & ~63u) * kLineSlot;
+  }
   const uint64_t n = (uint64_t)*a.list_len;
-  const uint32_t waves = gridDim.x * (kStepThreads / 64);
+  const uint32_t waves = gridDim.x * (kThreads / 64);
   WaveQueue wq;
   wq_init(wq);
   Lane<T> L;
   Outbox<T> O;
   O.what = 0;
+  ChildLine<T> cl;
+  cl.ln = kNoLine;
+  cl.mask = 0;
+  cl.first = ChildLine<T>::kPieces;
+  cl.eol = false;
   T q = T(-1);
   int64_t obase = 0;
   bool have = false;
@@ -958,13 +1058,28 @@ __global__ void __launch_bounds__(kStepThreads) k_write_lepton(StepArgs<T> a) {
       q = a.species + L.part == 0 ? T(-1) : T(1);
       have = true;
     }
-    if (!__any(have)) break;
+    if (!__any(have)) break;  // every lane's last half line went out with its parent's last trip
+    bool fin = false;
     if (have) {
-      const bool fin = lepton_iter<T, true>(a, lt, L, q, obase, O);
+      fin = lepton_iter<T, true>(a, lt, L, q, obase, O);
       if (fin) stage_final<T>(a, L, true, false, true, O);
+      if constexpr (kStage) {
+        if (O.what & kOutChild) {
+          line_put<T>(wave_slots + lane_id() * kLineSlot, cl, a.out_rec[0], O.at, O.r);
+          if (a.positions) {
+            T* qp = a.out_pos[0] + 4 * O.at;
+            qp[0] = O.x[0];
+            qp[1] = O.x[1];
+            qp[2] = O.x[2];
+            qp[3] = T(0);
+          }
+          O.what &= ~kOutChild;
+        }
+      }
       flush<T>(a, lt.src, O);
       if (fin) have = false;
     }
+    if constexpr (kStage) line_flush<T>(wave_slots, owners[threadIdx.x >> 6], cl, fin);
   }
 }
 
@@ -1406,13 +1521,13 @@ __global__ void k_append_records(SpeciesView<T> d, int64_t at, const Rec<T>* rec
 
 // ------------------------------------------------------------------ explicit instantiations via launchers
 template <typename K, typename A>
-hipError_t launch_step_kernel(K kernel, const A& a, int grid, size_t lds, hipStream_t st) {
+hipError_t launch_step_kernel(K kernel, const A& a, int grid, size_t lds, hipStream_t st, int threads = kStepThreads) {
   if (lds > 65536) {
     const hipError_t e =
         hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kStepThreads), lds, st, a);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 template <typename T, bool kPhoton>
@@ -1422,10 +1537,16 @@ hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t 
   return launch_step_kernel(&k_count_lepton<T, false>, a, grid, lds, st);
 }
 template <typename T, bool kPhoton>
-hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
+hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st, bool stage) {
   if (kPhoton) return launch_step_kernel(&k_write_photon<T>, a, grid, lds, st);
-  if (a.from_main) return launch_step_kernel(&k_write_lepton<T, true>, a, grid, lds, st);
-  return launch_step_kernel(&k_write_lepton<T, false>, a, grid, lds, st);
+  if constexpr (sizeof(T) == 4) {  // FP64 keeps its tables in HBM and its registers do not fit 1024 threads
+    if (stage) {
+      if (a.from_main) return launch_step_kernel(&k_write_lepton<T, true, true>, a, grid, lds, st, kWriteThreads);
+      return launch_step_kernel(&k_write_lepton<T, false, true>, a, grid, lds, st, kWriteThreads);
+    }
+  }
+  if (a.from_main) return launch_step_kernel(&k_write_lepton<T, true, false>, a, grid, lds, st);
+  return launch_step_kernel(&k_write_lepton<T, false, false>, a, grid, lds, st);
 }
 template <typename T>
 hipError_t launch_count_photon_merged(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
@@ -1513,10 +1634,10 @@ template hipError_t launch_count<float, false>(const StepArgs<float>&, int, size
 template hipError_t launch_count<float, true>(const StepArgs<float>&, int, size_t, hipStream_t);
 template hipError_t launch_count<double, false>(const StepArgs<double>&, int, size_t, hipStream_t);
 template hipError_t launch_count<double, true>(const StepArgs<double>&, int, size_t, hipStream_t);
-template hipError_t launch_write<float, false>(const StepArgs<float>&, int, size_t, hipStream_t);
-template hipError_t launch_write<float, true>(const StepArgs<float>&, int, size_t, hipStream_t);
-template hipError_t launch_write<double, false>(const StepArgs<double>&, int, size_t, hipStream_t);
-template hipError_t launch_write<double, true>(const StepArgs<double>&, int, size_t, hipStream_t);
+template hipError_t launch_write<float, false>(const StepArgs<float>&, int, size_t, hipStream_t, bool);
+template hipError_t launch_write<float, true>(const StepArgs<float>&, int, size_t, hipStream_t, bool);
+template hipError_t launch_write<double, false>(const StepArgs<double>&, int, size_t, hipStream_t, bool);
+template hipError_t launch_write<double, true>(const StepArgs<double>&, int, size_t, hipStream_t, bool);
 template hipError_t launch_merge_photons<float>(const MergeArgs<float>&, hipStream_t);
 template hipError_t launch_level_pass<float>(const SpeciesView<float>&, int64_t, int, double, int64_t, int, double*,
                                                 LevelState*, hipStream_t);
