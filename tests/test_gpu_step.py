@@ -153,6 +153,19 @@ def test_cascade_fp64_parity(env):
 
 
 def test_cascade_fp32_parity(env):
+    _check_cascade_fp32(env)
+
+
+def test_cascade_fp32_without_staging(env):
+    """FP32 emission tables too large for the write kernel's LDS staging area
+    beside them (70 x 320 CDF nodes, 94 KB): the write kernel falls back to
+    512-thread blocks that store each record directly, and the cascade must
+    agree with the oracle as on the staged path."""
+    torch, sf, _ = env
+    _check_cascade_fp32((torch, sf, sf.Tables(sf.default_table_cfg(rad_cols=320))))
+
+
+def _check_cascade_fp32(env):
     wl, st, ost, gmh, gah, om, oa = _cascade(env, "float32", 20_000)
     m = _match_all(gah, oa, gmh, om)
     flips = tot = 0
