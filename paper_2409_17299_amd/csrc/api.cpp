@@ -424,8 +424,10 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   const size_t stage_off = line_stage_offset(sizeof(SrcTable), sizeof(T) == 4, tab->view.rate[0].n,
                                              tab->view.cdf[0].rows32 * tab->view.cdf[0].cols32);
   const bool stage = !photon && sizeof(T) == 4 && stage_off + kLineStageBytes + kWriteThreads <= kMaxLdsBytes;
-  const int wthreads = stage ? kWriteThreads : kStepThreads;
-  const int wgrid = photon ? grid : (int)std::min<int64_t>((n + wthreads - 1) / wthreads, S->num_cu);
+  // as many blocks as 512-thread blocks would need, at most one per CU: a
+  // small launch still spreads over as many CUs (waves without work leave
+  // at once)
+  const int wgrid = photon ? grid : (int)std::min<int64_t>((n + kStepThreads - 1) / kStepThreads, S->num_cu);
   e = photon ? launch_write<T, true>(a, wgrid, lds, st)
              : launch_write<T, false>(a, wgrid, stage ? stage_off + kLineStageBytes : lds, st, stage);
   if (e != hipSuccess) {
