@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -180,6 +181,14 @@ qed_status ensure_merge_tiles(Scratch* s, int64_t tiles) {
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// SFQED_WRITE_STAGING=0 makes the lepton write kernel store every child record
+// directly (512-thread blocks) instead of staging it in LDS, so that the two
+// paths can be compared byte for byte; both write the same records.
+bool write_staging_enabled() {
+  const char* v = std::getenv("SFQED_WRITE_STAGING");
+  return !(v && v[0] == '0');
+}
 
 template <typename T>
 SpeciesView<T> view_of(const qed_species& s) {
@@ -423,7 +432,8 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   // runs kStepThreads threads and stores each record piece by piece.
   const size_t stage_off = line_stage_offset(sizeof(SrcTable), sizeof(T) == 4, tab->view.rate[0].n,
                                              tab->view.cdf[0].rows32 * tab->view.cdf[0].cols32);
-  const bool stage = !photon && sizeof(T) == 4 && stage_off + kLineStageBytes + kWriteThreads <= kMaxLdsBytes;
+  const bool stage = !photon && sizeof(T) == 4 && write_staging_enabled() &&
+                     stage_off + kLineStageBytes + kWriteThreads <= kMaxLdsBytes;
   // as many blocks as 512-thread blocks would need, at most one per CU: a
   // small launch still spreads over as many CUs (waves without work leave
   // at once)

@@ -87,3 +87,32 @@ def test_photon_capacity():
     torch.cuda.synchronize()
     assert rc == 2
     assert main[2].count <= main[2].capacity
+
+
+def test_staged_records_equal_direct_stores(monkeypatch):
+    """The FP32 lepton write kernel stages child records in LDS and writes them
+    in half lines; with SFQED_WRITE_STAGING=0 it stores each record directly
+    (512-thread blocks).  Staging changes how the records reach memory, not
+    what they hold: every appended record, every main array and every count
+    must be identical, on the same tables, over several generation rounds."""
+    torch, sf = need_gpu()
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 400), np.arange(0, 4_000_000, 400),
+                                                  np.arange(0, 2_000_000, 400)])
+    tabs = sf.Tables()
+    cfg = sf.step_cfg(push=False, gamma_min=2.0)
+    runs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("SFQED_WRITE_STAGING", flag)
+        main, fields, app = build(sf, torch, wl, torch.float32)
+        rc, st = sf.step(tabs, main, fields, app, wl.dt, 11, 0, cfg)
+        torch.cuda.synchronize()
+        assert rc == 0
+        runs.append((st, [arrays(m) for m in main], [a.records() for a in app], [a.count for a in app]))
+    (sa, ma, ra, ca), (sb, mb, rb, cb) = runs
+    assert sa.n_emit == sb.n_emit and sa.n_pair == sb.n_pair and sa.n_rounds == sb.n_rounds and ca == cb
+    print(f"{sa.n_emit} photons, {sa.n_pair} pairs, {sa.n_rounds} rounds: identical with and without staging")
+    assert sa.n_emit > 100_000 and sa.n_rounds >= 5
+    for s in range(3):
+        assert np.array_equal(ra[s], rb[s]), s
+        for name in ma[s]:
+            assert np.array_equal(ma[s][name], mb[s][name]), (s, name)
