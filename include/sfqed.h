@@ -27,6 +27,10 @@
  * therefore not overlap on the GPU: issue them on one stream, or synchronise
  * before switching streams.
  *
+ * Environment: SFQED_WRITE_STAGING=0 makes the FP32 step store each child
+ * record directly instead of staging it in LDS (the same records, slower); it
+ * exists so that the two paths can be compared.
+ *
  * Errors: every function returns a qed_status and never aborts.  Invalid
  * arguments are rejected before any work is queued.
  */
