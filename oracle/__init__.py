@@ -22,6 +22,9 @@ import numpy as np
 _DIR = Path(__file__).resolve().parent
 _SRC = _DIR / "sfqed_oracle.cpp"
 _LIB = _DIR / "liboracle.so"
+# SFQED_ORACLE_LIB names another build of the same source (the tests build
+# copies with a deliberate mistake planted, to show that the pins catch it)
+_LIB_OVERRIDE = os.environ.get("SFQED_ORACLE_LIB")
 
 ELECTRON, POSITRON, PHOTON = 0, 1, 2
 
@@ -64,9 +67,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not _LIB.exists():
-            build(force=False)
-        L = C.CDLL(str(_LIB))
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            if not _LIB.exists():
+                build(force=False)
+            L = C.CDLL(str(_LIB))
         d, i64, p = C.c_double, C.c_int64, C.c_void_p
         for name, res, args in [
             ("orc_philox", None, [p, p, p]),
@@ -77,6 +83,7 @@ def lib():
             ("orc_spec_rad", d, [d, d, C.c_int]),
             ("orc_spec_pair", d, [d, d, C.c_int]),
             ("orc_spec_rad_many", None, [p, p, i64, p]),
+            ("orc_spec_pair_many", None, [p, p, i64, p]),
             ("orc_rate_rad", d, [d, C.c_int]),
             ("orc_rate_pair", d, [d, C.c_int]),
             ("orc_rate_rad_many", None, [p, i64, p]),
@@ -152,6 +159,15 @@ def spec_rad_many(chi, delta) -> np.ndarray:
     d = np.ascontiguousarray(np.broadcast_to(np.asarray(delta, dtype=np.float64), c.shape))
     o = np.empty_like(d)
     lib().orc_spec_rad_many(_ptr(c), _ptr(d), d.size, _ptr(o))
+    return o
+
+
+def spec_pair_many(chi, xi) -> np.ndarray:
+    """dW_pair/d(xi) * eps/alpha at many (chi, xi)."""
+    c = np.ascontiguousarray(chi, dtype=np.float64)
+    x = np.ascontiguousarray(np.broadcast_to(np.asarray(xi, dtype=np.float64), c.shape))
+    o = np.empty_like(x)
+    lib().orc_spec_pair_many(_ptr(c), _ptr(x), x.size, _ptr(o))
     return o
 
 

@@ -626,6 +626,11 @@ void orc_spec_rad_many(const double* chi, const double* d, int64_t n, double* ou
   for (int64_t i = 0; i < n; ++i) out[i] = spec_rad(chi[i], d[i], 1.0 - d[i], false);
 }
 
+void orc_spec_pair_many(const double* chi, const double* xi, int64_t n, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) out[i] = spec_pair(chi[i], xi[i], 1.0 - xi[i], false);
+}
+
 // W * gamma / alpha and W * eps / alpha
 double orc_rate_rad(double chi, int def) { return rate_rad_reduced(chi, def != 0); }
 double orc_rate_pair(double chi, int def) { return rate_pair_reduced(chi, def != 0); }
