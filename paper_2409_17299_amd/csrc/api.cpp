@@ -208,8 +208,9 @@ SpeciesView<T> view_of(const qed_species& s) {
 }
 
 template <typename T>
-FieldView<T> fields_of(const qed_fields& f) {
+FieldView<T> fields_of(const qed_fields& f, int64_t n) {
   FieldView<T> v;
+  v.n = n;
   v.ex = static_cast<const T*>(f.ex);
   v.ey = static_cast<const T*>(f.ey);
   v.ez = static_cast<const T*>(f.ez);
@@ -326,7 +327,7 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   a.from_main = from_main ? 1 : 0;
   a.n0 = n0;
   a.n = n;
-  for (int k = 0; k < 3; ++k) a.f[k] = fields_of<T>(ens->f[k]);
+  for (int k = 0; k < 3; ++k) a.f[k] = fields_of<T>(ens->f[k], ens->s[k].count);
   int64_t* cursor;
   if (photon) {
     a.out_rec[0] = static_cast<Rec<T>*>(app[0].rec);
@@ -595,6 +596,10 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
     ens->s[1].count += app[1].count;
     ens->s[2].count = photons;
   }
+  if (dev_stats[kStatBadRoot]) {
+    set_error("an appended record's root names no particle of the ensemble (corrupted append buffer)");
+    return QED_ERR_ARG;
+  }
   if (dev_stats[kStatCapped]) {
     set_error("a particle reached max_events");
     return QED_ERR_EVENT_CAP;
@@ -602,24 +607,32 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   return QED_OK;
 }
 
+}  // namespace
+
+// The merge on scratch words the caller provides (see MergeScratch in lib.h):
+// leptons never die, so their records are appended after the input ensemble;
+// photons that died are dropped and the appended survivors follow, one stable
+// compaction with a decoupled look-back over tiles of kMergeTile photons.
 template <typename T>
-qed_status merge_impl(qed_ensemble* ens, const qed_append* app, hipStream_t st) {
-  Scratch* S = scratch_for_current_device();
-  if (!S) return QED_ERR_HIP;
-  std::lock_guard<std::mutex> lk(S->mu);
+qed_status merge_on(qed_ensemble* ens, const qed_append* app, hipStream_t st, const MergeScratch& ms) {
   const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
-  // leptons never die: their records are appended after the input ensemble
   for (int s = 0; s < 2; ++s)
     if (ens->s[s].count + app[s].count > ens->s[s].capacity) {
       set_error("merge: lepton capacity");
       return QED_ERR_CAPACITY;
     }
+  const int64_t ntot = ens->s[2].count + app[2].count;
+  const int64_t tiles = (ntot + kMergeTile - 1) / kMergeTile;
+  if (tiles > ms.tiles) {
+    set_error("merge: " + std::to_string(ntot) + " photons exceed the scratch (" + std::to_string(ms.tiles) +
+              " tiles of " + std::to_string(kMergeTile) + ")");
+    return QED_ERR_CAPACITY;
+  }
   // photons: survivors are compacted in place, so they must fit.  When the
   // capacity holds every photon that could survive there is nothing to check;
   // otherwise count the survivors first.
-  if (ens->s[2].count + app[2].count > ens->s[2].capacity) {
-    SFQED_HIP(hipMemsetAsync(S->ctrl + kAliveCount, 0, sizeof(uint64_t), st));
-    auto* cnt = reinterpret_cast<unsigned long long*>(S->ctrl + kAliveCount);
+  if (ntot > ens->s[2].capacity) {
+    auto* cnt = reinterpret_cast<unsigned long long*>(ms.alive);
     SFQED_HIP(launch_count_alive(ens->s[2].alive, ens->s[2].count, cnt, st));
     SFQED_HIP(launch_count_alive_rec<T>(static_cast<const Rec<T>*>(app[2].rec), app[2].count, cnt, st));
     uint64_t alive_total = 0;
@@ -633,24 +646,8 @@ qed_status merge_impl(qed_ensemble* ens, const qed_append* app, hipStream_t st) 
   for (int s = 0; s < 2; ++s)
     SFQED_HIP(launch_append_records<T>(view_of<T>(ens->s[s]), ens->s[s].count, static_cast<const Rec<T>*>(app[s].rec),
                                        static_cast<const T*>(app[s].pos), app[s].count, positions ? 1 : 0, st));
-  const int64_t ntot = ens->s[2].count + app[2].count;
   int64_t new_photons = 0;
   if (ntot > 0) {
-    const int64_t tiles = (ntot + kMergeTile - 1) / kMergeTile;
-    if (tiles > S->tiles_cap) {
-      if (S->state_c) {
-        SFQED_HIP(hipDeviceSynchronize());
-        (void)hipFree(S->state_c);
-        (void)hipFree(S->state_f);
-      }
-      SFQED_HIP(hipMalloc(&S->state_c, sizeof(uint64_t) * tiles));
-      SFQED_HIP(hipMalloc(&S->state_f, sizeof(uint64_t) * tiles));
-      SFQED_HIP(hipMemset(S->state_c, 0, sizeof(uint64_t) * tiles));
-      SFQED_HIP(hipMemset(S->state_f, 0, sizeof(uint64_t) * tiles));
-      S->tiles_cap = tiles;
-      S->epoch = 0;
-    }
-    SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t), st));
     MergeArgs<T> m;
     m.main = view_of<T>(ens->s[2]);
     m.app = static_cast<const Rec<T>*>(app[2].rec);
@@ -658,23 +655,63 @@ qed_status merge_impl(qed_ensemble* ens, const qed_append* app, hipStream_t st) 
     m.n_main = ens->s[2].count;
     m.n_app = app[2].count;
     m.positions = positions ? 1 : 0;
-    m.state = S->state_c;
-    m.epoch = next_epoch(S, st);
-    if (!m.epoch) {
-      set_error("clearing the look-back words failed");
-      return QED_ERR_HIP;
-    }
-    m.ticket = reinterpret_cast<unsigned long long*>(S->ctrl);
+    m.state = ms.state;
+    m.epoch = ms.epoch;
+    m.ticket = reinterpret_cast<unsigned long long*>(ms.ticket);
     m.num_tiles = tiles;
-    m.out_count = reinterpret_cast<int64_t*>(S->ctrl + kMergeCount);
+    m.out_count = reinterpret_cast<int64_t*>(ms.count);
     SFQED_HIP(launch_merge_photons<T>(m, st));
-    SFQED_HIP(hipMemcpyAsync(&new_photons, S->ctrl + kMergeCount, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SFQED_HIP(hipMemcpyAsync(&new_photons, ms.count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   }
   SFQED_HIP(hipStreamSynchronize(st));
   ens->s[0].count += app[0].count;
   ens->s[1].count += app[1].count;
   ens->s[2].count = new_photons;
   return QED_OK;
+}
+bool merge_args_ok(const qed_ensemble* ens, const qed_append* app) {
+  if (!ens || !app || (ens->dtype != QED_F32 && ens->dtype != QED_F64)) {
+    set_error("merge: null argument or invalid dtype");
+    return false;
+  }
+  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
+  for (int s = 0; s < 3; ++s) {
+    if (!species_ok(ens->s[s], s == 2, positions) || !append_ok(app[s], positions) || app[s].count < 0 ||
+        app[s].count > app[s].capacity) {
+      set_error("merge: invalid species " + std::to_string(s));
+      return false;
+    }
+  }
+  return true;
+}
+
+template qed_status merge_on<float>(qed_ensemble*, const qed_append*, hipStream_t, const MergeScratch&);
+template qed_status merge_on<double>(qed_ensemble*, const qed_append*, hipStream_t, const MergeScratch&);
+
+namespace {
+
+template <typename T>
+qed_status merge_impl(qed_ensemble* ens, const qed_append* app, hipStream_t st) {
+  Scratch* S = scratch_for_current_device();
+  if (!S) return QED_ERR_HIP;
+  std::lock_guard<std::mutex> lk(S->mu);
+  const int64_t tiles = (ens->s[2].count + app[2].count + kMergeTile - 1) / kMergeTile;
+  qed_status rc = ensure_merge_tiles(S, tiles);
+  if (rc != QED_OK) return rc;
+  SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t), st));
+  SFQED_HIP(hipMemsetAsync(S->ctrl + kAliveCount, 0, sizeof(uint64_t), st));
+  MergeScratch ms;
+  ms.state = S->state_c;
+  ms.tiles = S->tiles_cap;
+  ms.epoch = next_epoch(S, st);
+  if (!ms.epoch) {
+    set_error("clearing the look-back words failed");
+    return QED_ERR_HIP;
+  }
+  ms.ticket = S->ctrl;
+  ms.count = S->ctrl + kMergeCount;
+  ms.alive = S->ctrl + kAliveCount;
+  return merge_on<T>(ens, app, st, ms);
 }
 
 // Resampling after the merge (qed_resample): per species, the leveling
@@ -970,13 +1007,7 @@ qed_status qed_step_merged(const qed_tables* tab, const qed_step_cfg* cfg, qed_e
 }
 
 qed_status qed_merge(qed_ensemble* ens, const qed_append app[3], void* stream) {
-  if (!ens || !app) return QED_ERR_ARG;
-  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
-  for (int s = 0; s < 3; ++s) {
-    if (!species_ok(ens->s[s], s == 2, positions) || !append_ok(app[s], positions) || app[s].count < 0 ||
-        app[s].count > app[s].capacity)
-      return QED_ERR_ARG;
-  }
+  if (!merge_args_ok(ens, app)) return QED_ERR_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (ens->dtype == QED_F32) return merge_impl<float>(ens, app, st);
   if (ens->dtype == QED_F64) return merge_impl<double>(ens, app, st);
@@ -1029,10 +1060,10 @@ qed_status qed_eval_particles(const qed_tables* t, int species, qed_dtype dtype,
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype == QED_F32)
     SFQED_HIP(launch_eval_particles<float>(t->view, species, (const float*)px, (const float*)py, (const float*)pz,
-                                           fields_of<float>(*f), n, (float*)chi_out, (float*)w_out, st));
+                                           fields_of<float>(*f, n), n, (float*)chi_out, (float*)w_out, st));
   else if (dtype == QED_F64)
     SFQED_HIP(launch_eval_particles<double>(t->view, species, (const double*)px, (const double*)py,
-                                            (const double*)pz, fields_of<double>(*f), n, (double*)chi_out,
+                                            (const double*)pz, fields_of<double>(*f, n), n, (double*)chi_out,
                                             (double*)w_out, st));
   else
     return QED_ERR_ARG;

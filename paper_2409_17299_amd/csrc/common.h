@@ -109,6 +109,7 @@ template <typename T>
 struct FieldView {
   const T *ex, *ey, *ez, *bx, *by, *bz;
   int64_t stride;
+  int64_t n;  // entries per array when stride = 1
 };
 
 // Appended particle: one 16-byte-aligned record (the layout of qed_rec32 /

@@ -46,4 +46,20 @@ struct qed_tables {
 
 namespace sfqed {
 qed_status build_tables(const qed_table_cfg& cfg, hipStream_t stream, qed_tables* t);
+
+// Scratch words of one merge, provided by the caller: look-back words (tiles
+// of them, stamped with epochs; `epoch` must differ from every epoch the
+// words still hold) and three control words, the first and third zero on the
+// stream before the merge.
+struct MergeScratch {
+  uint64_t* state;
+  int64_t tiles;
+  uint32_t epoch;
+  uint64_t* ticket;  // tile counter (zero)
+  uint64_t* count;   // photons after the merge (written by the last tile)
+  uint64_t* alive;   // survivor count when the capacity is tight (zero)
+};
+template <typename T>
+qed_status merge_on(qed_ensemble* ens, const qed_append* app, hipStream_t st, const MergeScratch& ms);
+bool merge_args_ok(const qed_ensemble* ens, const qed_append* app);
 }

@@ -48,6 +48,7 @@ constexpr int kMergeTile = kMergeThreads * kMergeItems;
 constexpr int kStatMaxEvents = 0;
 constexpr int kStatCapped = 1;
 constexpr int kStatEventParticles = 2;  // + 0 leptons, + 1 photons
+constexpr int kStatBadRoot = 4;         // a record's root named no particle of the ensemble
 
 // A launch covers up to two source ranges ("parts"): electrons and positrons
 // go together (part 0 e-, part 1 e+), photons alone (part 0).  Particle k of
@@ -58,10 +59,11 @@ constexpr int kStatEventParticles = 2;  // + 0 leptons, + 1 photons
 // both source ranges and the fields of the three species into this table in
 // LDS when they start (see step.hip); it precedes the tables in the dynamic LDS.
 enum SrcWord : int { kPx, kPy, kPz, kX, kY, kZ, kW, kTau, kId, kAlive, kNev, kRec, kPos, kBegin, kSrcWords };
-enum FieldWord : int { kEx, kEy, kEz, kBx, kBy, kBz, kStride, kFieldWords };
+enum FieldWord : int { kEx, kEy, kEz, kBx, kBy, kBz, kStride, kFieldCount, kFieldWords };
 struct SrcTable {
   uint64_t part[2][kSrcWords];    // the two source ranges of the launch
   uint64_t field[3][kFieldWords];  // the fields of each species
+  uint64_t stats;                  // the launch's statistics words (device address)
   uint64_t pad;                    // to a multiple of 16 bytes
 };
 static_assert(sizeof(SrcTable) % 16 == 0, "LDS layout");

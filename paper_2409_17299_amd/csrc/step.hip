@@ -21,6 +21,7 @@
 // particle in event order -- the same for every run and every grid size.
 
 #include "lib.h"
+#include "line_rule.h"
 #include "physics.h"
 #include "step.h"
 
@@ -133,6 +134,7 @@ __device__ __forceinline__ void fill_field(uint64_t* w, const FieldView<T>& f) {
   w[kBy] = (uint64_t)f.by;
   w[kBz] = (uint64_t)f.bz;
   w[kStride] = (uint64_t)f.stride;
+  w[kFieldCount] = (uint64_t)f.n;
 }
 
 // one thread per entry (the caller synchronises the block afterwards)
@@ -144,6 +146,10 @@ __device__ __forceinline__ void stage_sources(const StepArgs<T>& a, SrcTable* t)
     case 2: fill_field<T>(t->field[0], a.f[0]); break;
     case 3: fill_field<T>(t->field[1], a.f[1]); break;
     case 4: fill_field<T>(t->field[2], a.f[2]); break;
+    case 5:
+      t->stats = (uint64_t)a.stats;
+      t->pad = 0;
+      break;
     default: break;
   }
 }
@@ -166,11 +172,21 @@ struct Lane {
 };
 
 // E and B of the particle's root (children keep the fields of the particle
-// they descend from; the fields are constant over the step)
+// they descend from; the fields are constant over the step).  A root that
+// names no particle (species > 2 or an index past the species' fields: only a
+// corrupted append record has one) gets no fields, so the particle has no
+// events, and raises a statistics flag that the host reports as an error.
 template <typename T>
 __device__ __forceinline__ void load_fields(const SrcTable* src, uint32_t root, T (&E)[3], T (&B)[3]) {
-  const uint64_t* f = src->field[root >> 30];
-  const int64_t o = f[kStride] ? (int64_t)(root & 0x3FFFFFFFu) : 0;
+  const uint32_t sp = root >> 30;
+  const uint64_t* f = src->field[sp < 3 ? sp : 0];
+  const int64_t idx = (int64_t)(root & 0x3FFFFFFFu);
+  if (sp >= 3 || (f[kStride] && idx >= (int64_t)f[kFieldCount])) {
+    atomicOr(gptr<unsigned long long>(src->stats) + kStatBadRoot, 1ull);
+    E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = T(0);
+    return;
+  }
+  const int64_t o = f[kStride] ? idx : 0;
   E[0] = gptr<const T>(f[kEx])[o];
   E[1] = gptr<const T>(f[kEy])[o];
   E[2] = gptr<const T>(f[kEz])[o];
@@ -934,46 +950,17 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
 }
 
 // ------------------------------------------------------------------ write kernels
-// The half line a lane is filling with its parent's child records: global
-// 16-byte piece p goes to slot p mod kLinePieces of half line p / kLinePieces.
-// A record that runs past the end of the half line keeps its tail pieces in
-// registers until the half line has been written.
+// Child records are staged per lane in LDS, kLinePieces 16-byte pieces (a
+// 64-byte half line of the append buffer) at a time, by the rule of
+// line_rule.h, and each half line is written out by kLinePieces lanes.
 template <typename T>
-struct ChildLine {
-  static constexpr int kPieces = (int)(sizeof(Rec<T>) / 16);
-  static_assert(kPieces <= kLinePieces, "a record spans at most two half lines");
-  uint64_t ln;      // global half-line index (address / 64), kNoLine when empty
-  uint32_t mask;    // pieces of the half line that hold data
-  int32_t first;    // first piece of the record held in `ov` (kPieces: none)
-  bool eol;         // the last record reached the end of the half line: write it out
-  uint4 ov[kPieces];
-};
-constexpr uint64_t kNoLine = ~0ull;
+using ChildLine = LineState<uint4, (int)(sizeof(Rec<T>) / 16)>;
 
 template <typename T>
-__device__ __forceinline__ void line_put(uint4* slot, ChildLine<T>& cl, const Rec<T>* base, int64_t o,
-                                         const Rec<T>& r) {
-  constexpr int kP = ChildLine<T>::kPieces;
+__device__ __forceinline__ void stage_child(uint4* slot, ChildLine<T>& cl, const Rec<T>* base, int64_t o,
+                                            const Rec<T>& r) {
   const RecBits<T> b = rec_pack<T>(r);
-  const uint64_t p0 = reinterpret_cast<uint64_t>(base + o) >> 4;
-  const int q0 = (int)(p0 & (kLinePieces - 1));
-  // Records of one parent are contiguous and a half line is written out as
-  // soon as a record reaches its end, so p0 lies in half line ln whenever ln
-  // is set.  (A parent's first half line can start in the middle, so a full
-  // mask is not the test.)
-  if (cl.ln == kNoLine) cl.ln = p0 >> kLineShift;
-  cl.first = kP;
-  cl.eol = q0 + kP >= kLinePieces;
-#pragma unroll
-  for (int k = 0; k < kP; ++k) {
-    if (q0 + k < kLinePieces) {
-      slot[q0 + k] = b.c[k];
-      cl.mask |= 1u << (q0 + k);
-    } else {
-      cl.ov[k] = b.c[k];
-      if (cl.first == kP) cl.first = k;
-    }
-  }
+  line_put<kLinePieces>(slot, cl, reinterpret_cast<uint64_t>(base + o) >> 4, b.c);
 }
 
 // Writes the half line of every lane whose last record reached the end of it
@@ -981,10 +968,9 @@ __device__ __forceinline__ void line_put(uint4* slot, ChildLine<T>& cl, const Re
 // per half line.  Called by the whole wave.
 template <typename T>
 __device__ __forceinline__ void line_flush(uint4* wave_slots, uint8_t* owners, ChildLine<T>& cl, bool fin) {
-  constexpr int kP = ChildLine<T>::kPieces;
   constexpr uint32_t kPerRound = 64 / kLinePieces;
   const int lane = lane_id();
-  bool ready = cl.ln != kNoLine && (fin || cl.eol);
+  bool ready = line_ready(cl, fin);
   uint64_t rm = __ballot(ready);
   while (rm) {
     const uint32_t r = (uint32_t)__popcll(rm);
@@ -998,25 +984,7 @@ __device__ __forceinline__ void line_flush(uint4* wave_slots, uint8_t* owners, C
       if (g < r && ((om >> piece) & 1u))
         gptr<uint4>(oln << (kLineShift + 4))[piece] = wave_slots[owner * kLineSlot + piece];
     }
-    if (ready) {
-      cl.mask = 0;
-      cl.eol = false;
-      if (cl.first < kP) {  // the record's tail starts the next half line
-        cl.ln += 1;
-        uint4* slot = wave_slots + lane * kLineSlot;
-#pragma unroll
-        for (int k = 0; k < kP; ++k)
-          if (k >= cl.first) {
-            slot[k - cl.first] = cl.ov[k];
-            cl.mask |= 1u << (k - cl.first);
-          }
-        cl.first = kP;
-        ready = fin;
-      } else {
-        cl.ln = kNoLine;
-        ready = false;
-      }
-    }
+    if (ready) ready = line_advance(wave_slots + lane * kLineSlot, cl, fin);
     rm = __ballot(ready);
   }
 }
@@ -1041,10 +1009,7 @@ __global__ void __launch_bounds__(kStage ? kWriteThreads : kStepThreads) k_write
   Outbox<T> O;
   O.what = 0;
   ChildLine<T> cl;
-  cl.ln = kNoLine;
-  cl.mask = 0;
-  cl.first = ChildLine<T>::kPieces;
-  cl.eol = false;
+  line_init(cl);
   T q = T(-1);
   int64_t obase = 0;
   bool have = false;
@@ -1065,7 +1030,7 @@ __global__ void __launch_bounds__(kStage ? kWriteThreads : kStepThreads) k_write
       if (fin) stage_final<T>(a, L, true, false, true, O);
       if constexpr (kStage) {
         if (O.what & kOutChild) {
-          line_put<T>(wave_slots + lane_id() * kLineSlot, cl, a.out_rec[0], O.at, O.r);
+          stage_child<T>(wave_slots + lane_id() * kLineSlot, cl, a.out_rec[0], O.at, O.r);
           if (a.positions) {
             T* qp = a.out_pos[0] + 4 * O.at;
             qp[0] = O.x[0];
