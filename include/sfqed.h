@@ -229,6 +229,19 @@ qed_status qed_step(const qed_tables *tab, const qed_step_cfg *cfg, qed_ensemble
  * device-to-host copy). */
 qed_status qed_merge(qed_ensemble *ens, const qed_append app[3], void *stream);
 
+/* qed_merge for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same merge, with the same results and errors, whose look-back words and
+ * counters live in a fixed array of 1 MiB + 256 B in the library's device
+ * memory instead of its growing scratch.  The array is set up (its address
+ * taken and cleared) on the first call on each device and every device the
+ * library runs on keeps it until the process ends.  It calls no hipMalloc or
+ * hipFree.  Limit: ens->s[2].count + app[2].count <= 268,435,456 photons
+ * (2^17 tiles of 2048), else QED_ERR_ARG before any work.  All calls on one
+ * device share its array: calls that overlap on one GPU race (issue them on
+ * one stream, or synchronise between them).  Blocking like qed_merge. */
+qed_status qed_merge_noalloc(qed_ensemble *ens, const qed_append app[3], void *stream);
+
 /* qed_step followed by qed_merge, with the photons merged inside the step
  * (Algorithm 2, then the merge of Sec. 4.2): the input photons are compacted
  * once their round is done, and every appended photon that survives the step

@@ -154,6 +154,7 @@ def lib():
             "qed_step": (C.c_int, [v, C.POINTER(StepCfg), C.POINTER(CEnsemble), C.POINTER(CAppend), C.c_double,
                                    C.c_uint64, C.c_uint32, C.POINTER(StepStats), v]),
             "qed_merge": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CAppend), v]),
+            "qed_merge_noalloc": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CAppend), v]),
             "qed_step_merged": (C.c_int, [v, C.POINTER(StepCfg), C.POINTER(CEnsemble), C.POINTER(CAppend),
                                           C.c_double, C.c_uint64, C.c_uint32, C.POINTER(StepStats), v]),
             "qed_resample_cfg_default": (None, [C.POINTER(ResampleCfg)]),
@@ -477,10 +478,12 @@ def step_merged(tables: Tables, main: list, fields: list, app: list, dt: float, 
     return rc, st
 
 
-def merge(main: list, fields: list, app: list, stream=None):
+def merge(main: list, fields: list, app: list, stream=None, noalloc: bool = False):
+    """qed_merge, or qed_merge_noalloc (scratch in a fixed device array) when noalloc is set."""
     e = _ensemble(main, fields)
     a = (CAppend * 3)(*[s.c() for s in app])
-    _check(lib().qed_merge(C.byref(e), a, _stream(stream)))
+    fn = lib().qed_merge_noalloc if noalloc else lib().qed_merge
+    _check(fn(C.byref(e), a, _stream(stream)))
     for k in range(3):
         main[k].count = int(e.s[k].count)
 

@@ -77,3 +77,22 @@ def test_grid_argument_errors_without_device(L):
     b_bad = sf.box((0, 0, 0), (float("nan"), 0, 0))
     g_ok_shape = sf.CGrid1d(sf.F32, 8, 0.0, 1.0, *([C.c_void_p(16)] * 6))  # never dereferenced: the box fails first
     assert L.qed_gather_fields(C.byref(e), C.byref(g_ok_shape), C.byref(b_bad), out, None) == 1
+
+
+def test_merge_noalloc_limit_without_device(L):
+    """qed_merge_noalloc refuses more photons than its fixed scratch holds
+    before any HIP call (the pointers below are never dereferenced)."""
+    import paper_2409_17299_amd as sf
+    fake = C.c_void_p(256)
+    e = sf.CEnsemble()
+    e.dtype = sf.F32
+    for s in range(3):
+        sp = e.s[s]
+        sp.px = sp.py = sp.pz = sp.w = sp.tau = sp.id = sp.alive = fake
+        sp.count, sp.capacity = 0, 1
+    n = (1 << 28) + 1  # one photon past 2^17 tiles of 2048
+    e.s[2].count = e.s[2].capacity = n
+    a = (sf.CAppend * 3)(*[sf.CAppend(fake, None, 0, 1) for _ in range(3)])
+    assert L.qed_merge_noalloc(C.byref(e), a, None) == 1
+    assert b"limit" in L.qed_last_error()
+    assert L.qed_merge_noalloc(None, None, None) == 1
