@@ -539,7 +539,9 @@ def main(argv=None):
     ms = el * 1e3 / args.steps
     S = sum_stats(stats)
     log(f"timed: {args.steps} steps in {el:.3f} s ({ms:.2f} ms/step); per-kernel ms "
-        f"{dict(zip(sf.StepStats.KERNELS, [round(v / args.steps, 3) for v in S['kernel_ms']]))}")
+        f"{dict(zip(sf.StepStats.KERNELS, [round(v / args.steps, 3) for v in S['kernel_ms']]))}; "
+        f"lepton launches written from the event log {S['log_replays']}, by the direct write kernel "
+        f"{S['log_reruns']}")
 
     n_particles = sum(dw.n)
     events = (S["n_emit"] + S["n_pair"]) / args.steps

@@ -199,6 +199,8 @@ typedef struct {
   int64_t kernel_launches[5];
   int64_t kernel_particles[5];      /* particles in the launches' ranges */
   int64_t event_particles[2];       /* particles with events: leptons, photons */
+  int64_t log_replays;              /* lepton launches written from the count pass's event log */
+  int64_t log_reruns;               /* lepton launches whose log did not fit (tables re-run) */
 } qed_step_stats;
 
 /* Draws tau = -ln(u) for every particle with tau < 0 (u from Philox4x32-10,

@@ -76,7 +76,8 @@ class StepStats(C.Structure):
     _fields_ = [("n_emit", C.c_int64), ("n_pair", C.c_int64), ("n_new", C.c_int64 * 3), ("n_rounds", C.c_int64),
                 ("max_events", C.c_int64), ("required_capacity", C.c_int64 * 3), ("n_launches", C.c_int64),
                 ("kernel_ms", C.c_double * 5), ("kernel_launches", C.c_int64 * 5),
-                ("kernel_particles", C.c_int64 * 5), ("event_particles", C.c_int64 * 2)]
+                ("kernel_particles", C.c_int64 * 5), ("event_particles", C.c_int64 * 2),
+                ("log_replays", C.c_int64), ("log_reruns", C.c_int64)]
 
     KERNELS = ("count_lepton", "scan", "write_lepton", "count_photon", "write_photon")
 

@@ -58,6 +58,13 @@ struct Scratch {
   uint64_t* state_m = nullptr;  // look-back words of the merged photon count pass, with their own epochs
   int64_t tiles_m_cap = 0;
   uint32_t epoch_m = 0;
+  // the lepton count pass's event log (replayed by the write pass): a pool
+  // that grows to the largest launch's need, and one head word per wave
+  int64_t* offsets_k = nullptr;  // first-child offset of every particle of a launch
+  char* log_pool = nullptr;
+  uint64_t log_cap = 0;
+  uint64_t* log_head = nullptr;
+  int64_t log_waves = 0;
   std::mutex mu;
 };
 
@@ -97,11 +104,13 @@ qed_status ensure_scratch(Scratch* s, int64_t n) {
       (void)hipFree(s->counts);
       (void)hipFree(s->offsets);
       (void)hipFree(s->list);
+      (void)hipFree(s->offsets_k);
       s->counts = nullptr;
     }
     SFQED_HIP(hipMalloc(&s->counts, sizeof(int32_t) * cap));
     SFQED_HIP(hipMalloc(&s->offsets, sizeof(int64_t) * cap));
     SFQED_HIP(hipMalloc(&s->list, sizeof(int32_t) * cap));
+    SFQED_HIP(hipMalloc(&s->offsets_k, sizeof(int64_t) * cap));
     s->cap = cap;
   }
   const int64_t tiles = (std::max(n, s->cap) + kScanTile - 1) / kScanTile + 1;
@@ -181,6 +190,51 @@ qed_status ensure_merge_tiles(Scratch* s, int64_t tiles) {
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// SFQED_WRITE_REPLAY=0 turns the event log off: the lepton write kernel then
+// re-runs every particle with events from the tables (the same results).
+bool write_replay_enabled() {
+  const char* v = std::getenv("SFQED_WRITE_REPLAY");
+  return !(v && v[0] == '0');
+}
+
+// Head words for the waves of the largest lepton count launch (two blocks of
+// kStepThreads per CU).
+qed_status ensure_log_heads(Scratch* s) {
+  const int64_t waves = (int64_t)s->num_cu * 2 * (kStepThreads / 64);
+  if (s->log_head && s->log_waves >= waves) return QED_OK;
+  if (s->log_head) {
+    SFQED_HIP(hipDeviceSynchronize());
+    (void)hipFree(s->log_head);
+    s->log_head = nullptr;
+  }
+  SFQED_HIP(hipMalloc(&s->log_head, sizeof(uint64_t) * waves));
+  s->log_waves = waves;
+  return QED_OK;
+}
+
+// After a step whose lepton launches needed `need` bytes of event log: grow
+// the pool to 5/4 of that (whole MiB) when it is short, as long as that takes
+// at most half of the free device memory; otherwise launches that need more
+// keep the direct write kernel.  Runs with the stream idle.
+void grow_log(Scratch* s, uint64_t need) {
+  if (need <= s->log_cap) return;
+  const uint64_t want = ((need + need / 4) + (1ull << 20) - 1) & ~((1ull << 20) - 1);
+  if (s->log_pool) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(s->log_pool);
+    s->log_pool = nullptr;
+    s->log_cap = 0;
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || want > free_b / 2) return;
+  if (hipMalloc(&s->log_pool, want) != hipSuccess) {
+    s->log_pool = nullptr;
+    (void)hipGetLastError();
+    return;
+  }
+  s->log_cap = want;
+}
 
 // SFQED_WRITE_STAGING=0 makes the lepton write kernel store every child record
 // directly (512-thread blocks) instead of staging it in LDS, so that the two
@@ -366,6 +420,17 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
     a.dst_ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot);
     a.pair_cursor = reinterpret_cast<int64_t*>(S->ctrl + kCurLepton);
   }
+  // leptons: the count pass logs its events and the replay writes from the
+  // log (the direct write kernel still runs the launch if the log overflows)
+  if (!photon && write_replay_enabled()) {
+    if ((rc = ensure_log_heads(S)) != QED_OK) return rc;
+    a.log_on = 1;
+    a.log_pool = S->log_pool;
+    a.log_cap = S->log_pool ? S->log_cap : 0;
+    a.log_head = S->log_head;
+    a.log_ctl = reinterpret_cast<unsigned long long*>(S->ctrl + *slot + 2 * kQueueWords + 4);
+    a.offsets_k = S->offsets_k;
+  }
   a.dt = dt;
   a.seed = seed;
   a.step = step;
@@ -404,6 +469,7 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   s.ticket = reinterpret_cast<unsigned long long*>(S->ctrl + *slot + 2 * kQueueWords);
   s.num_tiles = (n + kScanTile - 1) / kScanTile;
   s.event_particles = reinterpret_cast<unsigned long long*>(S->ctrl + kStats + kStatEventParticles + p);
+  s.offsets_k = a.log_on ? S->offsets_k : nullptr;
   *slot += kLaunchWords;
 
   const int k_count = photon ? 3 : 0, k_write = photon ? 4 : 2;
@@ -439,8 +505,12 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   // small launch still spreads over as many CUs (waves without work leave
   // at once)
   const int wgrid = photon ? grid : (int)std::min<int64_t>((n + kStepThreads - 1) / kStepThreads, S->num_cu);
-  e = photon ? launch_write<T, true>(a, wgrid, lds, st)
-             : launch_write<T, false>(a, wgrid, stage ? stage_off + kLineStageBytes : lds, st, stage);
+  // with the event log: the replay (count launch's grid), then the direct
+  // write kernel, which returns at once unless the log overflowed
+  e = a.log_on ? launch_replay<T>(a, grid, st) : hipSuccess;
+  if (e == hipSuccess)
+    e = photon ? launch_write<T, true>(a, wgrid, lds, st)
+               : launch_write<T, false>(a, wgrid, stage ? stage_off + kLineStageBytes : lds, st, stage);
   if (e != hipSuccess) {
     set_error(std::string("write kernel: ") + hipGetErrorString(e));
     return QED_ERR_HIP;
@@ -554,6 +624,7 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   uint64_t dev_stats[8];
   SFQED_HIP(hipMemcpyAsync(dev_stats, S->ctrl + kStats, sizeof(dev_stats), hipMemcpyDeviceToHost, st));
   SFQED_HIP(hipStreamSynchronize(st));
+  grow_log(S, dev_stats[kStatLogNeed]);  // later steps replay launches this one had to re-run
   local.n_emit = cur[0];
   local.n_pair = cur[1];
   local.n_new[0] = cur[1];
@@ -567,6 +638,8 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   local.n_launches = launches;
   local.event_particles[0] = (int64_t)dev_stats[kStatEventParticles];
   local.event_particles[1] = (int64_t)dev_stats[kStatEventParticles + 1];
+  local.log_replays = (int64_t)dev_stats[kStatReplays];
+  local.log_reruns = (int64_t)dev_stats[kStatReruns];
   log.collect(local.kernel_ms);
   app[0].count = std::min(cur[1], app[0].capacity);
   app[1].count = std::min(cur[1], app[1].capacity);

@@ -47,14 +47,16 @@ struct TableView {
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  One round maps
 // (c0, c1, c2, c3) to (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
-// lo(M0 c0)); the key advances by the Weyl increments between rounds.
+// lo(M0 c0)); the key advances by the Weyl increments between rounds.  Each
+// product is formed as one 64-bit value (one v_mad_u64_u32 on gfx950, where
+// separate high and low halves take two quarter-rate multiplies).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k.y, (uint32_t)p0);
     k.x += 0x9E3779B9u;
     k.y += 0xBB67AE85u;
   }

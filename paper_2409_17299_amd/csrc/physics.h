@@ -231,10 +231,10 @@ __device__ __forceinline__ void sigmoid_pair32(float z, float& p, float& q) {
   q = z >= 0.f ? small : r;
 }
 
-// Emission: delta and 1 - delta at chi (s = ln chi).  `tab` is the FP32 grid
-// (LDS or global).
-__device__ __forceinline__ void sample_rad32_s(const float* tab, const CdfView& c, float chi, float s_chi,
-                                               uint32_t k, float& d, float& omd) {
+// Emission: z = logit(delta) at chi (s = ln chi); delta and 1 - delta are
+// sigmoid(z) and sigmoid(-z).  `tab` is the FP32 grid (LDS or global).
+__device__ __forceinline__ float sample_rad32_z(const float* tab, const CdfView& c, float chi, float s_chi,
+                                                uint32_t k) {
   const float x = logit_r32(k);
   float ux = (x - c.x0_32) * c.inv_hx32;
   float extra = 0.f;
@@ -256,14 +256,24 @@ __device__ __forceinline__ void sample_rad32_s(const float* tab, const CdfView& 
   } else {
     q = grid_interp<float, float>(tab, c.rows32, c.cols32, us, ux);
   }
-  sigmoid_pair32(q + extra + s, d, omd);
+  return q + extra + s;
+}
+__device__ __forceinline__ void sample_rad32_s(const float* tab, const CdfView& c, float chi, float s_chi,
+                                               uint32_t k, float& d, float& omd) {
+  sigmoid_pair32(sample_rad32_z(tab, c, chi, s_chi, k), d, omd);
 }
 __device__ __forceinline__ void sample_rad32(const float* tab, const CdfView& c, float chi, uint32_t k, float& d,
                                              float& omd) {
   sample_rad32_s(tab, c, chi, logf(chi), k, d, omd);
 }
 
-__device__ __forceinline__ void sample_rad64(const CdfView& c, double chi, uint32_t k, double& d, double& omd) {
+// sigmoid(z) and sigmoid(-z) (FP64 path)
+__device__ __forceinline__ void sigmoid_pair64(double z, double& p, double& q) {
+  p = 1.0 / (1.0 + exp(-z));
+  q = 1.0 / (1.0 + exp(z));
+}
+
+__device__ __forceinline__ double sample_rad64_z(const CdfView& c, double chi, uint32_t k) {
   double lr, lrc;
   log_r64(k, lr, lrc);
   const double x = lr - lrc;
@@ -287,9 +297,10 @@ __device__ __forceinline__ void sample_rad64(const CdfView& c, double chi, uint3
   } else {
     q = grid_interp<double, double>(c.f64, c.rows64, c.cols64, us, ux);
   }
-  const double z = q + extra + s;
-  d = 1.0 / (1.0 + exp(-z));
-  omd = 1.0 / (1.0 + exp(z));
+  return q + extra + s;
+}
+__device__ __forceinline__ void sample_rad64(const CdfView& c, double chi, uint32_t k, double& d, double& omd) {
+  sigmoid_pair64(sample_rad64_z(c, chi, k), d, omd);
 }
 
 // Pairs: xi (electron) and 1 - xi (positron) at chi (s = ln chi).

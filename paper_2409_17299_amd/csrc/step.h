@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "event_log.h"
 
 namespace sfqed {
 
@@ -49,6 +50,23 @@ constexpr int kStatMaxEvents = 0;
 constexpr int kStatCapped = 1;
 constexpr int kStatEventParticles = 2;  // + 0 leptons, + 1 photons
 constexpr int kStatBadRoot = 4;         // a record's root named no particle of the ensemble
+constexpr int kStatLogNeed = 5;         // largest event log a lepton launch needed (bytes)
+constexpr int kStatReplays = 6;         // lepton launches written from the event log
+constexpr int kStatReruns = 7;          // lepton launches written by the direct write kernel
+
+// Event log of the lepton count pass, replayed by the write pass
+// (k_replay_lepton in step.hip; format in event_log.h).  Each wave of the
+// count launch writes its own sequence of trip records into blocks handed out
+// from one pool; log_ctl words of the launch: blocks handed out, overflow
+// flag, bytes the launch needed.
+constexpr int kLogUsed = 0, kLogOverflow = 1, kLogNeed = 2;
+// bytes of one lane's slot: an event's z and h in the step's dtype, the
+// uniform draw of its child's optical depth (32 bits) and the particle's
+// launch index, or a finished particle's optical depth (FP64)
+template <typename T>
+constexpr uint32_t log_slot_bytes() {
+  return sizeof(T) == 4 ? 16u : 32u;
+}
 
 // A launch covers up to two source ranges ("parts"): electrons and positrons
 // go together (part 0 e-, part 1 e+), photons alone (part 0).  Particle k of
@@ -103,6 +121,13 @@ struct StepArgs {
   uint32_t dst_epoch;
   unsigned long long* dst_ticket;   // tile counter, zero at launch
   int64_t* pair_cursor;             // pairs appended so far (the scan's cursor of a photon launch)
+  // lepton launches: the count pass's event log, replayed by the write pass
+  char* log_pool;                   // log blocks
+  uint64_t log_cap;                 // bytes of log_pool (0: the count pass only measures the log)
+  uint64_t* log_head;               // per wave of the count launch: 1 + byte offset of its first block, 0 = none
+  unsigned long long* log_ctl;      // the launch's log words (kLogUsed, kLogOverflow, kLogNeed), zero at launch
+  int32_t log_on;                   // 1: the count pass logs; the replay writes unless the log overflowed
+  int64_t* offsets_k;               // first-child offset of every particle of the launch (from the scan)
 };
 
 struct ScanArgs {
@@ -118,6 +143,7 @@ struct ScanArgs {
   unsigned long long* ticket;  // zero at launch
   int64_t num_tiles;
   unsigned long long* event_particles;  // += number of particles with events
+  int64_t* offsets_k;  // or null: the first-child offset of every particle
 };
 
 template <typename T>
@@ -172,6 +198,8 @@ template <typename T>
 hipError_t launch_count_photon_merged(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st);
 template <typename T, bool kPhoton>
 hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st, bool stage = false);
+template <typename T>
+hipError_t launch_replay(const StepArgs<T>& a, int grid, hipStream_t st);
 hipError_t launch_scan(const ScanArgs& s, hipStream_t st);
 template <typename T>
 hipError_t launch_merge_photons(const MergeArgs<T>& a, hipStream_t st);

@@ -169,6 +169,8 @@ struct Lane {
   int32_t j;
   bool capped;
   bool changed;  // state differs from what was loaded
+  T lz, lh;      // the last event's sampler value z and sub-interval h (logged by the count pass)
+  uint32_t lu;   // the last event's draw for the child's optical depth (logged)
 };
 
 // E and B of the particle's root (children keep the fields of the particle
@@ -196,9 +198,10 @@ __device__ __forceinline__ void load_fields(const SrcTable* src, uint32_t root, 
 }
 
 // Issues the loads of the state of particle k of the launch; a particle of the
-// input ensemble (kMain) also loads its fields, an appended particle finds them
-// through its root afterwards.  Positions are zero unless they are tracked.
-template <typename T, bool kMain>
+// input ensemble (kMain) also loads its fields (unless kFields is off), an
+// appended particle finds them through its root afterwards.  Positions are
+// zero unless they are tracked.
+template <typename T, bool kMain, bool kFields = true>
 __device__ __forceinline__ void load_state(const StepArgs<T>& a, const SrcTable* src, int64_t k, Lane<T>& L) {
   const bool p1 = k >= a.n0;
   const int part = p1 ? 1 : 0;
@@ -213,7 +216,7 @@ __device__ __forceinline__ void load_state(const StepArgs<T>& a, const SrcTable*
   if constexpr (kMain) {
     // the root is the particle itself: its fields load together with its state
     L.root = ((uint32_t)(a.species + part) << 30) | (uint32_t)i;
-    load_fields<T>(src, L.root, L.E, L.B);
+    if constexpr (kFields) load_fields<T>(src, L.root, L.E, L.B);
     L.p[0] = gptr<const T>(w[kPx])[i];
     L.p[1] = gptr<const T>(w[kPy])[i];
     L.p[2] = gptr<const T>(w[kPz])[i];
@@ -397,6 +400,20 @@ __device__ __forceinline__ void sample_of(const StepArgs<T>& a, const LdsTables&
   }
 }
 
+// The emission sampler split at its last step: z = logit(delta) from the
+// grids, then delta = sigmoid(z) and 1 - delta = sigmoid(-z).  The count pass
+// logs z, so the write pass replays the event without the grids.
+template <typename T>
+__device__ __forceinline__ T sample_rad_z(const StepArgs<T>& a, const LdsTables& lt, T chi, T s_chi, uint32_t k) {
+  if constexpr (sizeof(T) == 4) return sample_rad32_z(lt.cdf, a.tab.cdf[0], chi, s_chi, k);
+  else return sample_rad64_z(a.tab.cdf[0], chi, k);
+}
+template <typename T>
+__device__ __forceinline__ void sigmoid_of(T z, T& p, T& q) {
+  if constexpr (sizeof(T) == 4) sigmoid_pair32(z, p, q);
+  else sigmoid_pair64(z, p, q);
+}
+
 // ln chi for the FP32 path (the FP64 path takes its logarithms inside)
 template <typename T>
 __device__ __forceinline__ T log_chi(T chi) {
@@ -447,8 +464,9 @@ __device__ __forceinline__ void write_child(Rec<T>* out, T* pos, int64_t idx, co
 }
 
 // One sub-cycle of Algorithm 1 for a lepton.  Returns true when the particle
-// has reached the end of the step.
-template <typename T, bool kWrite>
+// has reached the end of the step.  kLog keeps what the write pass needs to
+// replay an event in L.lz, L.lh and L.lu.
+template <typename T, bool kWrite, bool kLog = false>
 __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTables& lt, Lane<T>& L, T q,
                                             int64_t out_base, Outbox<T>& O) {
   const T dtT = (T)a.dt;
@@ -478,8 +496,14 @@ __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTable
     chi_e = chi_of<T>(L.p, g2, L.E, L.B);
     s_e = log_chi<T>(chi_e);
   }
+  const T z = sample_rad_z<T>(a, lt, chi_e, s_e, u.x);
   T d, omd;
-  sample_of<T>(a, lt, 0, chi_e, s_e, u.x, d, omd);
+  sigmoid_of<T>(z, d, omd);
+  if constexpr (kLog) {
+    L.lz = z;
+    L.lh = h;
+    L.lu = u.z;
+  }
   if (kWrite) {
     const int64_t o = out_base + L.j;
     if (o < a.out_cap) {  // the photon: k = delta p, born here
@@ -662,43 +686,166 @@ __device__ __forceinline__ uint64_t wq_take(WaveQueue& q, bool need, uint64_t n,
   return got;
 }
 
+// ------------------------------------------------------------------ event log
+// With the log on, the lepton count pass records what the write pass needs
+// to replay each event without the tables (format in event_log.h): per trip
+// of a wave in which some lane had an event, or finished a particle that had
+// one, a record of the lanes that took a new particle and of the lanes with
+// an event, and per such lane a slot: the event's sampler value
+// z = logit(delta), sub-interval h, the uniform draw of the child's optical
+// depth and the particle's launch index, or the finished particle's optical
+// depth.  A particle without events is never logged.  When the pool runs out, the wave stops writing, raises
+// the overflow flag and the direct write kernel does the launch's writes;
+// every wave still adds up the bytes it would have needed, so that the host
+// can grow the pool.
+// Wave-uniform state of one wave's log, kept in 32-bit words (scalar
+// registers are scarce in the count kernel).
+struct LogWriter {
+  uint32_t blk;   // current block (index in the pool, in units of kLogBlock)
+  uint32_t pos;   // next record position in the block
+  uint32_t recs;  // records of this wave, written or not
+  uint32_t state; // 0: no block yet, 1: writing, 2: the pool ran out
+};
+
+// A lane's slot of a record (FP32: one 16-byte piece; FP64: two).
+template <typename T>
+struct LogSlot {
+  uint4 c[log_slot_bytes<T>() / 16];
+};
+
+template <typename T>
+__device__ __forceinline__ LogSlot<T> log_event_slot(T z, T h, uint32_t u, int64_t k) {
+  LogSlot<T> s;
+  if constexpr (sizeof(T) == 4) {
+    s.c[0] = make_uint4(fbits(z), fbits(h), u, (uint32_t)k);
+  } else {
+    const uint64_t zb = __builtin_bit_cast(uint64_t, z), hb = __builtin_bit_cast(uint64_t, h);
+    const uint64_t kb = (uint64_t)k;
+    s.c[0] = make_uint4(lo32(zb), hi32(zb), lo32(hb), hi32(hb));
+    s.c[1] = make_uint4(u, 0u, lo32(kb), hi32(kb));
+  }
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ LogSlot<T> log_final_slot(double tau) {
+  LogSlot<T> s;
+  const uint64_t t = __builtin_bit_cast(uint64_t, tau);
+  s.c[0] = make_uint4(lo32(t), hi32(t), 0u, 0u);
+  if constexpr (sizeof(T) == 8) s.c[1] = make_uint4(0u, 0u, 0u, 0u);
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ void log_trip(const StepArgs<T>& a, LogWriter& w, uint32_t wave, bool ev,
+                                         bool fin_with_events, bool fresh, const Lane<T>& L) {
+  constexpr uint32_t S = log_slot_bytes<T>();
+  constexpr uint64_t R = log_record_bytes(S);
+  constexpr uint32_t kPer = (uint32_t)log_records_per_block(S);
+  const uint64_t m_part = __ballot(ev || fin_with_events);
+  if (!m_part) return;
+  const uint64_t m_new = __ballot(fresh && ev), m_ev = __ballot(ev);
+  w.recs += 1;
+  if (w.state == 2) return;
+  const int lane = lane_id();
+  if (w.state == 0 || w.pos + 1 >= kPer) {  // the block's last position is kept for a marker
+    uint32_t b = 0;
+    if (lane == 0) b = (uint32_t)(atomicAdd(a.log_ctl + kLogUsed, 1ull));
+    b = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
+    const uint64_t blk = (uint64_t)b * kLogBlock;
+    if (blk + kLogBlock > a.log_cap) {
+      if (lane == 0) atomicOr(a.log_ctl + kLogOverflow, 1ull);
+      w.state = 2;
+      return;
+    }
+    if (lane == 0) {
+      if (w.state == 1) {
+        char* m = a.log_pool + (uint64_t)w.blk * kLogBlock + (uint64_t)w.pos * R;
+        *reinterpret_cast<uint4*>(m) =
+            make_uint4(lo32(kLogMarkNew), hi32(kLogMarkNew), lo32(kLogMarkJump), hi32(kLogMarkJump));
+        *reinterpret_cast<uint64_t*>(m + 16) = blk;
+      } else {
+        a.log_head[wave] = blk + 1;
+      }
+    }
+    w.state = 1;
+    w.blk = b;
+    w.pos = 0;
+  }
+  char* rec = a.log_pool + (uint64_t)w.blk * kLogBlock + (uint64_t)w.pos * R;
+  if (lane == 0) *reinterpret_cast<uint4*>(rec) = make_uint4(lo32(m_new), hi32(m_new), lo32(m_ev), hi32(m_ev));
+  if (ev || fin_with_events) {
+    const LogSlot<T> sl = ev ? log_event_slot<T>(L.lz, L.lh, L.lu, L.k) : log_final_slot<T>(L.tau);
+    uint4* d = reinterpret_cast<uint4*>(rec + 16 + (uint64_t)S * lane);
+#pragma unroll
+    for (int c = 0; c < (int)(S / 16); ++c) d[c] = sl.c[c];
+  }
+  w.pos += 1;
+}
+
+template <typename T>
+__device__ __forceinline__ void log_close(const StepArgs<T>& a, const LogWriter& w, uint32_t wave) {
+  constexpr uint64_t R = log_record_bytes(log_slot_bytes<T>());
+  constexpr uint64_t kPer = log_records_per_block(log_slot_bytes<T>());
+  if (lane_id() != 0) return;
+  if (w.state == 0) a.log_head[wave] = 0;
+  else if (w.state == 1)
+    *reinterpret_cast<uint4*>(a.log_pool + (uint64_t)w.blk * kLogBlock + (uint64_t)w.pos * R) =
+        make_uint4(lo32(kLogMarkNew), hi32(kLogMarkNew), lo32(kLogMarkEnd), hi32(kLogMarkEnd));
+  // the blocks this wave's records take (each block keeps its last position
+  // for a marker), plus one for the end marker
+  if (w.recs) atomicAdd(a.log_ctl + kLogNeed, (unsigned long long)(w.recs / (kPer - 1) + 2) * kLogBlock);
+}
+
 // ------------------------------------------------------------------ count kernels
 // Leptons: event counts vary from 0 to hundreds, so lanes refill.
 // A particle of the input ensemble (kMain) has its fields at its own index;
 // an appended one finds them through its root, a second load after its record.
-template <typename T, bool kMain>
+// kLog: the pass also writes the event log (above).
+template <typename T, bool kMain, bool kLog>
 __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1) k_count_lepton(StepArgs<T> a) {
   extern __shared__ float lds[];
   const LdsTables lt = stage_tables<T, false>(a, lds);
   const uint64_t n = (uint64_t)a.n;
   const uint32_t waves = gridDim.x * (kStepThreads / 64);
+  const uint32_t wave = blockIdx.x * (kStepThreads / 64) + (threadIdx.x >> 6);
   WaveQueue wq;
   wq_init(wq);
   Lane<T> L;
   Outbox<T> O;
   O.what = 0;
+  LogWriter lw;
+  lw.blk = lw.pos = lw.recs = lw.state = 0;
   T q = T(-1);
   bool have = false;
   int32_t local_max = 0;
   bool capped = false;
   while (true) {
     const uint64_t k = wq_take(wq, !have, n, a.queue, waves);
+    bool fresh = false;
     if (!have && k < n) {
       load_state<T, kMain>(a, lt.src, (int64_t)k, L);
       if (!kMain) load_fields<T>(lt.src, L.root, L.E, L.B);
       q = a.species + L.part == 0 ? T(-1) : T(1);
       have = true;
+      fresh = true;
     }
     if (!__any(have)) break;
-    if (have && lepton_iter<T, false>(a, lt, L, q, 0, O)) {
-      O.what = kOutCount;
-      stage_final<T>(a, L, a.push != 0, false, L.j == 0, O);
-      flush<T>(a, lt.src, O);
-      local_max = L.j > local_max ? L.j : local_max;
-      capped |= L.capped;
-      have = false;
+    bool fin = false;
+    if (have) {
+      fin = lepton_iter<T, false, kLog>(a, lt, L, q, 0, O);
+      if (fin) {
+        O.what = kOutCount;
+        stage_final<T>(a, L, a.push != 0, false, L.j == 0, O);
+        flush<T>(a, lt.src, O);
+        local_max = L.j > local_max ? L.j : local_max;
+        capped |= L.capped;
+      }
     }
+    if constexpr (kLog) log_trip<T>(a, lw, wave, have && !fin, have && fin && L.j > 0, fresh, L);
+    if (fin) have = false;
   }
+  if constexpr (kLog) log_close<T>(a, lw, wave);
   for (int off = 32; off > 0; off >>= 1) {
     const int32_t o = __shfl_xor(local_max, off);
     local_max = o > local_max ? o : local_max;
@@ -947,6 +1094,14 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
     s.list[bf + j] = l_idx[j];
     s.offsets[bf + j] = bc + l_off[j];
   }
+  if (s.offsets_k) {  // every particle's first-child offset (read by the replay)
+    int64_t o = bc + pre_c + ic - my_c;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (k0 + i < s.n) s.offsets_k[k0 + i] = o;
+      o += c[i];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ write kernels
@@ -956,19 +1111,24 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(ScanArgs s) {
 template <typename T>
 using ChildLine = LineState<uint4, (int)(sizeof(Rec<T>) / 16)>;
 
-template <typename T>
+// kL pieces per line; a lane's slot holds kL + 1 pieces (the spare one puts
+// neighbouring slots in different banks)
+template <int kL, typename T>
 __device__ __forceinline__ void stage_child(uint4* slot, ChildLine<T>& cl, const Rec<T>* base, int64_t o,
                                             const Rec<T>& r) {
   const RecBits<T> b = rec_pack<T>(r);
-  line_put<kLinePieces>(slot, cl, reinterpret_cast<uint64_t>(base + o) >> 4, b.c);
+  line_put<kL>(slot, cl, reinterpret_cast<uint64_t>(base + o) >> 4, b.c);
 }
 
-// Writes the half line of every lane whose last record reached the end of it
-// (running past it or not) or whose parent finished (fin), kLinePieces lanes
-// per half line.  Called by the whole wave.
-template <typename T>
+// Writes the line of every lane whose last record reached the end of it
+// (running past it or not) or whose parent finished (fin), kL lanes per line.
+// Called by the whole wave.
+template <int kL, typename T>
 __device__ __forceinline__ void line_flush(uint4* wave_slots, uint8_t* owners, ChildLine<T>& cl, bool fin) {
-  constexpr uint32_t kPerRound = 64 / kLinePieces;
+  static_assert(kL == 4 || kL == 8, "half or whole 128-byte lines");
+  constexpr uint32_t kPerRound = 64 / kL;
+  constexpr int kShift = kL == 8 ? 3 : 2;
+  constexpr int kSlot = kL + 1;
   const int lane = lane_id();
   bool ready = line_ready(cl, fin);
   uint64_t rm = __ballot(ready);
@@ -976,22 +1136,30 @@ __device__ __forceinline__ void line_flush(uint4* wave_slots, uint8_t* owners, C
     const uint32_t r = (uint32_t)__popcll(rm);
     if (ready) owners[mbcnt(rm)] = (uint8_t)lane;
     for (uint32_t g0 = 0; g0 < r; g0 += kPerRound) {
-      const uint32_t g = g0 + (uint32_t)(lane >> kLineShift);
+      const uint32_t g = g0 + (uint32_t)(lane >> kShift);
       const int owner = g < r ? (int)owners[g] : lane;
       const uint64_t oln = __shfl(cl.ln, owner);
       const uint32_t om = __shfl(cl.mask, owner);
-      const int piece = lane & (kLinePieces - 1);
+      const int piece = lane & (kL - 1);
       if (g < r && ((om >> piece) & 1u))
-        gptr<uint4>(oln << (kLineShift + 4))[piece] = wave_slots[owner * kLineSlot + piece];
+        gptr<uint4>(oln << (kShift + 4))[piece] = wave_slots[owner * kSlot + piece];
     }
-    if (ready) ready = line_advance(wave_slots + lane * kLineSlot, cl, fin);
+    if (ready) ready = line_advance(wave_slots + lane * kSlot, cl, fin);
     rm = __ballot(ready);
   }
 }
 
+// The direct write kernel: re-runs every particle with events from the event
+// list.  With the event log on it only runs when the log overflowed (the
+// replay below does the writes otherwise).
 template <typename T, bool kMain, bool kStage>
 __global__ void __launch_bounds__(kStage ? kWriteThreads : kStepThreads) k_write_lepton(StepArgs<T> a) {
   constexpr int kThreads = kStage ? kWriteThreads : kStepThreads;
+  if (a.log_on) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&a.stats[kStatLogNeed], a.log_ctl[kLogNeed]);
+    if (!a.log_ctl[kLogOverflow]) return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.stats[kStatReruns], 1ull);
   extern __shared__ float lds[];
   __shared__ uint8_t owners[kStage ? kThreads / 64 : 1][64];
   const LdsTables lt = stage_tables<T, false>(a, lds);
@@ -1030,7 +1198,7 @@ __global__ void __launch_bounds__(kStage ? kWriteThreads : kStepThreads) k_write
       if (fin) stage_final<T>(a, L, true, false, true, O);
       if constexpr (kStage) {
         if (O.what & kOutChild) {
-          stage_child<T>(wave_slots + lane_id() * kLineSlot, cl, a.out_rec[0], O.at, O.r);
+          stage_child<kLinePieces, T>(wave_slots + lane_id() * kLineSlot, cl, a.out_rec[0], O.at, O.r);
           if (a.positions) {
             T* qp = a.out_pos[0] + 4 * O.at;
             qp[0] = O.x[0];
@@ -1044,7 +1212,182 @@ __global__ void __launch_bounds__(kStage ? kWriteThreads : kStepThreads) k_write
       flush<T>(a, lt.src, O);
       if (fin) have = false;
     }
-    if constexpr (kStage) line_flush<T>(wave_slots, owners[threadIdx.x >> 6], cl, fin);
+    if constexpr (kStage) line_flush<kLinePieces, T>(wave_slots, owners[threadIdx.x >> 6], cl, fin);
+  }
+}
+
+// advance_lepton with push and positions fixed at compile time (the replay is
+// instantiated for each combination, so that unused state takes no registers);
+// the same operations in the same order
+template <typename T, bool kPush, bool kPos>
+__device__ __forceinline__ void advance_lepton_ct(Lane<T>& L, T q, T h) {
+  if constexpr (kPush) boris<T>(L.p, q, L.E, L.B, h);
+  if constexpr (kPos) {
+    const T gi = T(1) / sqrt(T(1) + L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
+    L.x[0] += L.p[0] * gi * h;
+    L.x[1] += L.p[1] * gi * h;
+    L.x[2] += L.p[2] * gi * h;
+  }
+}
+
+// One event replayed from the log: the arithmetic of lepton_iter's event
+// branch with z, h and the child's optical depth taken from the log, so the
+// child record and the particle's state come out bit for bit the same.
+template <typename T, bool kPush, bool kPos>
+__device__ __forceinline__ void replay_event(const StepArgs<T>& a, Lane<T>& L, T q, T z, T h, uint32_t u,
+                                             int64_t obase, Outbox<T>& O) {
+  advance_lepton_ct<T, kPush, kPos>(L, q, h);
+  L.t += h;
+  T d, omd;
+  sigmoid_of<T>(z, d, omd);
+  const int64_t o = obase + L.j;
+  if (o < a.out_cap) {  // the photon: k = delta p, born here
+    const uint4 v = draw(a.seed, L.id, a.step, (uint32_t)L.j | 0x80000000u);
+    O.r.px = d * L.p[0];
+    O.r.py = d * L.p[1];
+    O.r.pz = d * L.p[2];
+    O.r.tb = L.t;
+    O.r.tau = exp_depth_t<T>(u);
+    O.r.id = (uint64_t)v.x | ((uint64_t)v.y << 32);
+    O.r.w = L.w;
+    O.r.root = L.root;
+    O.r.nev = 0;
+    O.r.alive = 1u;
+    if constexpr (kPos) {
+      O.x[0] = L.x[0];
+      O.x[1] = L.x[1];
+      O.x[2] = L.x[2];
+    }
+    O.at = o;
+    O.what = kOutChild;
+  }
+  L.p[0] *= omd;
+  L.p[1] *= omd;
+  L.p[2] *= omd;
+  L.changed = true;
+  ++L.j;
+}
+
+// The lepton write pass from the count pass's event log.  It runs the count
+// launch's grid, and wave w reads the records of count wave w: its lanes hold
+// the same particles on the same trips.  A new lane loads its particle, an
+// event lane replays the event and writes the child at the particle's first
+// child offset plus the event index, and a lane whose particle finished moves
+// it to the end of the step and stores its final state with the logged
+// optical depth.  No tables are needed, so LDS holds only the source table
+// and (FP32) a whole 128-byte line per lane for the child records, written
+// out by eight lanes per line.
+constexpr int kReplayLine = 8;
+template <typename T, bool kMain, bool kStage, bool kPush, bool kPos>
+__global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSimd : 1) k_replay_lepton(StepArgs<T> a) {
+  if (!a.log_on || a.log_ctl[kLogOverflow]) return;  // the direct write kernel does the writes
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.stats[kStatReplays], 1ull);
+  extern __shared__ float lds[];
+  __shared__ uint8_t owners[kStage ? kStepThreads / 64 : 1][64];
+  SrcTable* src = reinterpret_cast<SrcTable*>(lds);
+  stage_sources<T>(a, src);
+  __syncthreads();
+  constexpr int kSlot = kReplayLine + 1;
+  uint4* wave_slots = nullptr;
+  if constexpr (kStage)
+    wave_slots = reinterpret_cast<uint4*>(reinterpret_cast<char*>(lds) + sizeof(SrcTable)) +
+                 (threadIdx.x & ~63u) * kSlot;
+  const uint32_t wave = blockIdx.x * (kStepThreads / 64) + (threadIdx.x >> 6);
+  const uint64_t head = a.log_head[wave];
+  if (head == 0) return;
+  constexpr uint32_t S = log_slot_bytes<T>();
+  constexpr uint64_t R = log_record_bytes(S);
+  const T dtT = (T)a.dt;
+  const int lane = lane_id();
+  const uint64_t me = 1ull << lane;
+  uint64_t blk = head - 1;
+  uint32_t pos = 0;
+  // a record and, fetched while the current one is handled, the next
+  auto fetch = [&](uint32_t p, uint4& hd, LogSlot<T>& sl) {
+    const char* r = a.log_pool + blk + (uint64_t)p * R;
+    hd = *reinterpret_cast<const uint4*>(r);
+    const uint4* qs = reinterpret_cast<const uint4*>(r + 16 + (uint64_t)S * lane);
+#pragma unroll
+    for (int c = 0; c < (int)(S / 16); ++c) sl.c[c] = qs[c];
+  };
+  uint4 hd;
+  LogSlot<T> sl;
+  fetch(pos, hd, sl);
+  Lane<T> L;
+  Outbox<T> O;
+  O.what = 0;
+  ChildLine<T> cl;
+  line_init(cl);
+  T q = T(-1);
+  int64_t obase = 0;
+  bool have = false;
+  while (true) {
+    const uint64_t m_new = join64(hd.x, hd.y), m_ev = join64(hd.z, hd.w);
+    if (log_is_marker(m_new, m_ev)) {
+      if (m_ev == kLogMarkEnd) break;
+      blk = join64(__builtin_amdgcn_readlane((int)sl.c[0].x, 0), __builtin_amdgcn_readlane((int)sl.c[0].y, 0));
+      pos = 0;
+      fetch(pos, hd, sl);
+      continue;
+    }
+    // the next record (a record never sits at a block's last position)
+    uint4 hd_n;
+    LogSlot<T> sl_n;
+    fetch(pos + 1, hd_n, sl_n);
+    const bool ev = (m_ev & me) != 0;
+    const bool fin = have && !ev;
+    if (m_new & me) {
+      int64_t k;
+      if constexpr (sizeof(T) == 4) k = (int64_t)sl.c[0].w;
+      else k = (int64_t)join64(sl.c[1].z, sl.c[1].w);
+      load_state<T, kMain, kPush>(a, src, k, L);
+      if (!kMain && kPush) load_fields<T>(src, L.root, L.E, L.B);
+      if constexpr (!kPos) L.x[0] = L.x[1] = L.x[2] = T(0);
+      obase = a.offsets_k[k];
+      q = a.species + L.part == 0 ? T(-1) : T(1);
+      have = true;
+    }
+    if (ev) {
+      T z, h;
+      uint32_t u;
+      if constexpr (sizeof(T) == 4) {
+        z = __builtin_bit_cast(float, sl.c[0].x);
+        h = __builtin_bit_cast(float, sl.c[0].y);
+        u = sl.c[0].z;
+      } else {
+        z = __builtin_bit_cast(double, join64(sl.c[0].x, sl.c[0].y));
+        h = __builtin_bit_cast(double, join64(sl.c[0].z, sl.c[0].w));
+        u = sl.c[1].x;
+      }
+      replay_event<T, kPush, kPos>(a, L, q, z, h, u, obase, O);
+    } else if (fin) {
+      const double tf = __builtin_bit_cast(double, join64(sl.c[0].x, sl.c[0].y));
+      if (L.t < dtT) {  // no event before the end of the step (the count pass's last trip)
+        advance_lepton_ct<T, kPush, kPos>(L, q, dtT - L.t);
+        L.t = dtT;
+      }
+      L.tau = tf;
+      stage_final<T>(a, L, true, false, true, O);
+    }
+    if constexpr (kStage) {
+      if (O.what & kOutChild) {
+        stage_child<kReplayLine, T>(wave_slots + lane * kSlot, cl, a.out_rec[0], O.at, O.r);
+        if constexpr (kPos) {
+          T* qp = a.out_pos[0] + 4 * O.at;
+          qp[0] = O.x[0];
+          qp[1] = O.x[1];
+          qp[2] = O.x[2];
+          qp[3] = T(0);
+        }
+        O.what &= ~kOutChild;
+      }
+    }
+    flush<T>(a, src, O);
+    if constexpr (kStage) line_flush<kReplayLine, T>(wave_slots, owners[threadIdx.x >> 6], cl, fin);
+    if (fin) have = false;
+    hd = hd_n;
+    sl = sl_n;
+    pos += 1;
   }
 }
 
@@ -1498,8 +1841,12 @@ hipError_t launch_step_kernel(K kernel, const A& a, int grid, size_t lds, hipStr
 template <typename T, bool kPhoton>
 hipError_t launch_count(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
   if (kPhoton) return launch_step_kernel(&k_count_photon<T>, a, grid, lds, st);
-  if (a.from_main) return launch_step_kernel(&k_count_lepton<T, true>, a, grid, lds, st);
-  return launch_step_kernel(&k_count_lepton<T, false>, a, grid, lds, st);
+  if (a.log_on) {
+    if (a.from_main) return launch_step_kernel(&k_count_lepton<T, true, true>, a, grid, lds, st);
+    return launch_step_kernel(&k_count_lepton<T, false, true>, a, grid, lds, st);
+  }
+  if (a.from_main) return launch_step_kernel(&k_count_lepton<T, true, false>, a, grid, lds, st);
+  return launch_step_kernel(&k_count_lepton<T, false, false>, a, grid, lds, st);
 }
 template <typename T, bool kPhoton>
 hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st, bool stage) {
@@ -1513,6 +1860,26 @@ hipError_t launch_write(const StepArgs<T>& a, int grid, size_t lds, hipStream_t 
   if (a.from_main) return launch_step_kernel(&k_write_lepton<T, true, false>, a, grid, lds, st);
   return launch_step_kernel(&k_write_lepton<T, false, false>, a, grid, lds, st);
 }
+// The replay runs the count launch's grid (512-thread blocks); FP32 stages its
+// child records in LDS half lines.
+template <typename T, bool kMain>
+hipError_t launch_replay_main(const StepArgs<T>& a, int grid, hipStream_t st) {
+  constexpr bool kStage = sizeof(T) == 4;
+  const size_t lds = sizeof(SrcTable) + (kStage ? (size_t)kStepThreads * (kReplayLine + 1) * 16 : 0);
+  if (a.push) {
+    if (a.positions) return launch_step_kernel(&k_replay_lepton<T, kMain, kStage, true, true>, a, grid, lds, st);
+    return launch_step_kernel(&k_replay_lepton<T, kMain, kStage, true, false>, a, grid, lds, st);
+  }
+  if (a.positions) return launch_step_kernel(&k_replay_lepton<T, kMain, kStage, false, true>, a, grid, lds, st);
+  return launch_step_kernel(&k_replay_lepton<T, kMain, kStage, false, false>, a, grid, lds, st);
+}
+template <typename T>
+hipError_t launch_replay(const StepArgs<T>& a, int grid, hipStream_t st) {
+  return a.from_main ? launch_replay_main<T, true>(a, grid, st) : launch_replay_main<T, false>(a, grid, st);
+}
+template hipError_t launch_replay<float>(const StepArgs<float>&, int, hipStream_t);
+template hipError_t launch_replay<double>(const StepArgs<double>&, int, hipStream_t);
+
 template <typename T>
 hipError_t launch_count_photon_merged(const StepArgs<T>& a, int grid, size_t lds, hipStream_t st) {
   return launch_step_kernel(&k_count_photon_merged<T>, a, grid, lds, st);

@@ -101,6 +101,7 @@ def test_staged_records_equal_direct_stores(monkeypatch):
     tabs = sf.Tables()
     cfg = sf.step_cfg(push=False, gamma_min=2.0)
     runs = []
+    monkeypatch.setenv("SFQED_WRITE_REPLAY", "0")  # the direct write kernel, staged or not
     for flag in ("1", "0"):
         monkeypatch.setenv("SFQED_WRITE_STAGING", flag)
         main, fields, app = build(sf, torch, wl, torch.float32)
@@ -116,3 +117,66 @@ def test_staged_records_equal_direct_stores(monkeypatch):
         assert np.array_equal(ra[s], rb[s]), s
         for name in ma[s]:
             assert np.array_equal(ma[s][name], mb[s][name]), (s, name)
+
+
+def _replay_vs_direct(monkeypatch, sf, torch, wl, dtype, cfg, x=None, steps=1, merged=False):
+    """Runs the same steps with the write pass replayed from the count pass's
+    event log and with the direct write kernel; returns both results."""
+    tabs = sf.Tables()
+    runs = []
+    for flag in ("0", "1", "1"):  # the first logged run may size the log pool; the second must replay
+        monkeypatch.setenv("SFQED_WRITE_REPLAY", flag)
+        main, fields, app = build(sf, torch, wl, dtype, x)
+        sts = []
+        for k in range(steps):
+            fn = sf.step_merged if merged else sf.step
+            rc, st = fn(tabs, main, fields, app, wl.dt, 3, k, cfg)
+            assert rc == 0
+            if not merged:
+                sf.merge(main, fields, app)
+            sts.append(st)
+        torch.cuda.synchronize()
+        runs.append((sts, [arrays(m) for m in main], [a.records() for a in app], [m.count for m in main]))
+    direct, replay = runs[0], runs[2]
+    assert all(st.log_replays == 0 for st in direct[0])
+    assert all(st.log_replays > 0 and st.log_reruns == 0 for st in replay[0]), \
+        [(st.log_replays, st.log_reruns) for st in replay[0]]
+    for a, b in zip(direct[0], replay[0]):
+        assert (a.n_emit, a.n_pair, a.n_rounds) == (b.n_emit, b.n_pair, b.n_rounds)
+    assert direct[3] == replay[3]
+    for s in range(3):
+        assert np.array_equal(direct[2][s], replay[2][s]), s
+        for name in direct[1][s]:
+            assert np.array_equal(direct[1][s][name], replay[1][s][name]), (s, name)
+    return replay[0][-1], replay[3]
+
+
+@pytest.mark.parametrize("dtype_name", ["float32", "float64"])
+def test_replayed_writes_equal_direct_writes(monkeypatch, dtype_name):
+    """The lepton write pass replayed from the count pass's event log (z, h and
+    the child optical depth of every event, the final optical depth of every
+    particle) writes what the direct write kernel writes by re-running each
+    event from the tables: every record, array and count identical, over a
+    multi-round step with both processes."""
+    torch, sf = need_gpu()
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 400), np.arange(0, 4_000_000, 400),
+                                                  np.arange(0, 2_000_000, 400)])
+    st, counts = _replay_vs_direct(monkeypatch, sf, torch, wl, getattr(torch, dtype_name),
+                                   sf.step_cfg(push=False, gamma_min=2.0))
+    print(f"{dtype_name}: {st.n_emit} photons, {st.n_pair} pairs, {st.n_rounds} rounds, "
+          f"{st.log_replays} launches replayed: identical to the direct writes")
+    assert st.n_pair > 1000 and st.n_rounds >= 5
+
+
+def test_replayed_writes_with_push_and_positions(monkeypatch):
+    """The same with the Boris push and positions (the replay re-applies the
+    push over each logged sub-interval), three merged steps of the rotating
+    field cascade."""
+    torch, sf = need_gpu()
+    wl = synth.rotating_e(1_000_000, indices=np.arange(0, 1_000_000, 500))
+    rng = np.random.default_rng(9)
+    x = [rng.normal(0.0, 1e3, (sp.n, 3)) for sp in wl.species]
+    st, counts = _replay_vs_direct(monkeypatch, sf, torch, wl, torch.float32, sf.step_cfg(push=True), x=x,
+                                   steps=3, merged=True)
+    print(f"3 merged steps with push and positions: counts {counts}, identical to the direct writes")
+    assert counts[0] > wl.species[0].n
