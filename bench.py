@@ -33,9 +33,10 @@ def log(*a):
 
 
 # ----------------------------------------------------------------------------- algorithmic bytes
-def kernel_bytes(name: str, st: dict, n_main: list, n_step: int, merged: bool = True) -> float:
+def kernel_bytes(name: str, st: dict, n_main: list, n_step: int, merged: bool = True, push: bool = False) -> float:
     """Bytes the method must move in all launches of one kernel during n_step steps
-    (FP32 momenta/fields/times, FP64 optical depth, u64 ids; push off, no positions).
+    (FP32 momenta/fields/times, FP64 optical depth, u64 ids; no positions; with
+    push every lepton also writes its momentum back).
     merged: the photon count pass of appended photons writes each survivor into
     the main arrays (p 12, w 4, tau 8, id 8, alive 1) instead of its tau and
     count, and the event list (index 4, offset 8) of the others, so the scan
@@ -50,7 +51,7 @@ def kernel_bytes(name: str, st: dict, n_main: list, n_step: int, merged: bool = 
         # read p 12, E and B 24, tau 8, id 8 (+ root 4, t_birth 4 for children); write the
         # count 4 and, for particles without events, tau 8
         n = P[0]
-        return n * (52 + 4) + (n - main_l) * 8 + (n - ev_l) * 8
+        return n * (52 + 4) + (n - main_l) * 8 + (n - ev_l) * (8 + (12 if push else 0))
     if name == "scan":
         # read every count; write index and first-child offset of each particle with events
         return P[1] * 4 + (ev_l + (0 if merged else ev_p)) * (4 + 8)
@@ -280,6 +281,101 @@ def cascade_bench(sf, torch, steps: int, n_seeds: int, merged: bool = True) -> d
                        "ms_per_step_each": [round(x * 1e3, 2) for x in secs]}}
 
 
+def cascade_leg(sf, torch, n_seeds: int = 1_000_000, steps: int = 20) -> dict:
+    """The rotating-field cascade as an extra leg of the default run: push on,
+    merge every step, n_seeds electrons growing ~200x.  One untimed run sizes
+    the library's scratch, the second is reported: host time per step, and
+    the dominant kernel (HIP events in the library, on the step's stream) with
+    its algorithmic bytes against 8 TB/s."""
+    import synth
+    from paper_2409_17299_amd import cascade
+    wl = synth.rotating_e(n_seeds)
+    e0, wdt = wl.flags["e0"], wl.flags["omega_dt"]
+    tables = sf.Tables()
+    sp = [(s.p, s.w, s.tau, s.id) for s in wl.species]
+    cap = [n_seeds * 80, n_seeds * 80, n_seeds * 300]
+    app = [n_seeds * 20, n_seeds * 20, n_seeds * 80]
+    cfg = sf.step_cfg(push=True, nev=False, profile=True)
+    for rep in range(2):
+        counts, stats, secs, main, _ = cascade.run(tables, sp, wl.dt, steps,
+                                                   lambda k: synth.rotating_field(e0, wdt, k), cap, app,
+                                                   dtype=torch.float32, seed=0, cfg=cfg)
+        del main
+        torch.cuda.empty_cache()
+    S = sum_stats(stats)
+    n_main = [int(v) for v in counts[:-1].sum(axis=0)]  # input particles over all steps
+    kern = {}
+    for k, name in enumerate(sf.StepStats.KERNELS):
+        if S["kernel_launches"][k]:
+            b = kernel_bytes(name, S, n_main, 1, merged=True, push=True)
+            kern[name] = {"ms_total": round(S["kernel_ms"][k], 4), "launches": S["kernel_launches"][k],
+                          "gbs": round(b / (S["kernel_ms"][k] * 1e-3) / 1e9, 1)}
+    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    t = float(sum(secs))
+    particle_steps = float(counts[:-1].sum())
+    log(f"rotating-field cascade: {steps} steps in {t * 1e3:.1f} ms, {counts[0].sum()} -> {counts[-1].sum()} "
+        f"particles; dominant kernel {dom} {kern[dom]['ms_total']:.2f} ms")
+    return {"workload": "rotating_e", "seeds": n_seeds, "steps": steps, "push": True, "merge_every_step": True,
+            "dtype": "f32", "ms_per_step": round(t * 1e3 / steps, 3),
+            "particle_steps_per_s": round(particle_steps / t, 1),
+            "events_per_s": round(float(S["n_emit"] + S["n_pair"]) / t, 1),
+            "particles_first_last": [int(counts[0].sum()), int(counts[-1].sum())],
+            "growth_rate": cascade.growth_rate(counts, wl.dt, first=5),
+            "lepton_launches_from_event_log": S["log_replays"],
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4)},
+            "kernels": kern}
+
+
+def per_particle_leg(sf, torch, n_chunk: int = 20_000_000, passes: int = 10) -> dict:
+    """The per-particle kernels of the precision-sweep workload at scale: chi
+    and rate (qed_eval_particles) and the first event's energy fraction
+    (qed_sample), FP32 path, for electrons and photons with chi*
+    log-uniform in [1e-3, 1e3] in a static B.  One chunk of n_chunk particles
+    (half of each species) is generated once and evaluated `passes` times
+    (2e8 particle evaluations by default).  Algorithmic bytes per particle:
+    eval reads p 12 and E, B 24 and writes chi 4 and W 4; sample reads chi 4
+    and the uniform 4 and writes the fraction 4 (56 in all)."""
+    import numpy as np
+
+    import synth
+    tables = sf.Tables()
+    idx = np.arange(n_chunk // 2)
+    wl = synth.static_b_sweep(200_000_000, indices=[idx, idx, idx])
+    parts = []
+    for s, proc in ((0, 0), (2, 1)):
+        sp = wl.species[s]
+        st = sf.Store.from_arrays(sp.p, sp.w, sp.tau, sp.id, dtype=torch.float32, photon=s == 2)
+        f = sf.Fields.from_array(sp.fields, torch.float32)
+        k = torch.tensor(synth.bits32(0, 56 + s, sp.id).view(np.int32), device="cuda")
+        parts.append((s, proc, st, f, k))
+    del wl
+
+    def one_pass():
+        for s, proc, st, f, k in parts:
+            chi, _ = sf.eval_particles(tables, s, st, f)
+            sf.sample(tables, proc, chi, k)
+
+    one_pass()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(passes):
+        one_pass()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    n_eval = n_chunk * passes
+    gbs = 56.0 * n_eval / (ms * 1e-3) / 1e9
+    log(f"per-particle kernels: {n_eval:.2e} evaluations in {ms:.1f} ms, {gbs:.0f} GB/s")
+    return {"workload": "static_b_sweep", "chi_range": [1e-3, 1e3], "dtype": "f32",
+            "kernels": "k_eval_particles + k_sample", "particles_per_pass": n_chunk, "passes": passes,
+            "evaluations": n_eval, "ms": round(ms, 3), "particles_per_s": round(n_eval / (ms * 1e-3), 1),
+            "bytes_per_particle": 56,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+
+
 # ----------------------------------------------------------------------------- standing-wave test problem
 def standing_wave_bench(sf, torch, steps: int, n_seeds: int, target: int, e_min: float, merged: bool = True) -> dict:
     """The test problem of Sec. 5.1 on its grid: n_seeds e-/e+ at rest in a
@@ -449,6 +545,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--simd-stride", type=int, default=20, help="sample of the host-CPU baseline (host_simd)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the rotating-field cascade and per-particle legs of the default run")
     ap.add_argument("--two-call", action="store_true",
                     help="time qed_step followed by qed_merge instead of qed_step_merged (same results)")
     ap.add_argument("--workload", default="crossed_field",
@@ -567,13 +665,19 @@ def main(argv=None):
                       "positrons": dw.n[1], "photons": dw.n[2], "chi_range": [0.1, 100.0],
                       "energy_range": [1e2, 1e4], "dt": wl.dt, "processes": "emission+pair", "push": False,
                       "gamma_min": args.gamma_min, "precision": "fp32 particles/tables, fp64 optical depth",
-                      "events_per_step": events, "rounds": S["n_rounds"] / args.steps},
+                      "events_per_step": events, "rounds": S["n_rounds"] / args.steps,
+                      "lepton_writes": {"from_event_log": S["log_replays"], "direct": S["log_reruns"]}},
            "roofline": roof,
            "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                        for k, v in kern.items()}}
+    del dw
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("rotating-field cascade (push on, 1e6 seeds, 20 steps)")
+        out["rotating_cascade"] = cascade_leg(sf, torch)
+        log("per-particle kernels of the precision-sweep workload (2e8 evaluations)")
+        out["per_particle"] = per_particle_leg(sf, torch)
     if not args.no_surrogate:
-        del dw
-        torch.cuda.empty_cache()
         log("surrogate vs table: 1e8 emission events")
         out["surrogate"] = surrogate_comparison(sf, torch, tables)
     if not args.no_cpu:

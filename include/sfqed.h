@@ -54,7 +54,6 @@ typedef enum {
 } qed_status;
 
 typedef enum { QED_F32 = 0, QED_F64 = 1 } qed_dtype;
-typedef enum { QED_SAMPLER_TABLE = 0, QED_SAMPLER_MLP = 1 } qed_sampler;
 enum { QED_ELECTRON = 0, QED_POSITRON = 1, QED_PHOTON = 2 };
 enum { QED_EMISSION = 0, QED_PAIR = 1 };
 
@@ -68,6 +67,11 @@ enum { QED_EMISSION = 0, QED_PAIR = 1 };
  *    of g(s) = ln(W gamma / (alpha chi)) (emission) and
  *    ln(W eps/(alpha chi)) + 8/(3 chi) (pairs) over [rate_chi_min, rate_chi_max].
  *  - FP32 rates: cubic Hermite of the same g on rate_nodes uniform nodes.
+ *  - Above the tables (chi beyond the last Chebyshev segment, at least
+ *    rate_chi_max) both rates follow their chi^(2/3) limits as
+ *    exp(a chi^(-2/3)), a matched at the last node: within 2e-7 of the
+ *    quadrature up to chi = 1e10.  Below rate_chi_min emission uses the
+ *    classical series and pairs are zero.
  *  - Inverse CDFs: q = logit(delta) - ln chi (emission) and q = logit(xi)
  *    (pairs, xi <= 1/2 tabulated, the rest by symmetry) on a uniform grid in
  *    (ln chi, logit r); FP32 grids are staged in LDS by the step kernels, FP64
@@ -173,10 +177,12 @@ typedef struct {
   qed_fields f[3];
 } qed_ensemble;
 
+/* The step samples energy fractions from the inverse-CDF tables.  The
+ * learned surrogate (qed_sample_mlp below) is a standalone sampler: on this
+ * chip it is several times slower than the FP32 table, and inside the step
+ * each loop trip would have to evaluate the network for the whole wave. */
 typedef struct {
   int32_t emission, pair, push; /* processes on/off; push: Boris between events */
-  qed_sampler sampler;          /* QED_SAMPLER_MLP uses `mlp` inside its trained range */
-  const void *mlp;
   double gamma_min;             /* leptons with gamma < gamma_min do not emit (>= 1) */
   int64_t max_events;           /* per particle and step; reaching it is an error */
   int32_t profile;              /* 1: time every launch with HIP events into stats */

@@ -67,9 +67,8 @@ class CEnsemble(C.Structure):
 
 
 class StepCfg(C.Structure):
-    _fields_ = [("emission", C.c_int32), ("pair", C.c_int32), ("push", C.c_int32), ("sampler", C.c_int),
-                ("mlp", C.c_void_p), ("gamma_min", C.c_double), ("max_events", C.c_int64),
-                ("profile", C.c_int32), ("nev", C.c_int32)]
+    _fields_ = [("emission", C.c_int32), ("pair", C.c_int32), ("push", C.c_int32), ("gamma_min", C.c_double),
+                ("max_events", C.c_int64), ("profile", C.c_int32), ("nev", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -681,15 +680,6 @@ class Mlp:
         _check(lib().qed_sample_mlp(tables.handle, self.handle, _ptr(chi), _ptr(k), _ptr(out), chi.numel(),
                                     _stream(stream)))
         return out
-
-    def features(self, chi, r=None, logit_r=None):
-        """Network inputs for chi and r (numpy, float64 arithmetic)."""
-        chi = np.asarray(chi, dtype=np.float64)
-        if logit_r is None:
-            r = np.asarray(r, dtype=np.float64)
-            logit_r = np.log(r) - np.log1p(-r)
-        return np.stack([np.log(chi) * self.cfg.f1_scale + self.cfg.f1_shift,
-                         np.asarray(logit_r) * self.cfg.f2_scale], axis=1)
 
 
 def load_surrogate(path=None) -> np.ndarray:

@@ -1011,8 +1011,6 @@ void qed_step_cfg_default(qed_step_cfg* c) {
   c->emission = 1;
   c->pair = 1;
   c->push = 1;
-  c->sampler = QED_SAMPLER_TABLE;
-  c->mlp = nullptr;
   c->gamma_min = 1.0;
   c->max_events = 1 << 20;
   c->profile = 0;
@@ -1038,7 +1036,7 @@ qed_status qed_step(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble
     return QED_ERR_ARG;
   }
   if (!finite_pos(dt) || (ens->dtype != QED_F32 && ens->dtype != QED_F64) || !(cfg->gamma_min >= 1.0) ||
-      cfg->max_events < 1 || cfg->sampler != QED_SAMPLER_TABLE) {
+      cfg->max_events < 1) {
     set_error("invalid step configuration");
     return QED_ERR_ARG;
   }
@@ -1062,7 +1060,7 @@ qed_status qed_step_merged(const qed_tables* tab, const qed_step_cfg* cfg, qed_e
     return QED_ERR_ARG;
   }
   if (!finite_pos(dt) || (ens->dtype != QED_F32 && ens->dtype != QED_F64) || !(cfg->gamma_min >= 1.0) ||
-      cfg->max_events < 1 || cfg->sampler != QED_SAMPLER_TABLE) {
+      cfg->max_events < 1) {
     set_error("invalid step configuration");
     return QED_ERR_ARG;
   }

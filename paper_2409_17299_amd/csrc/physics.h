@@ -46,9 +46,21 @@ __device__ __forceinline__ void boris(T p[3], T q, const T E[3], const T B[3], T
 //   emission: g = ln(W_rad gamma / (alpha chi))
 //   pairs:    g = ln(W_pair eps / (alpha chi)) + 8 / (3 chi)
 // Below the table emission uses the two leading terms of the classical series
-// W gamma/alpha = 5 chi/(2 sqrt3) (1 - 8 sqrt3 chi/15) and pairs are zero;
-// above it ln(W/chi) continues with the chi^(-1/3) slope of both limits.
+// W gamma/alpha = 5 chi/(2 sqrt3) (1 - 8 sqrt3 chi/15) and pairs are zero.
+// Above it both rates approach their chi^(2/3) limits,
+//   W_rad gamma / alpha -> 14 Gamma(2/3) / 3^(7/3) chi^(2/3),
+//   W_pair eps / alpha  -> 15 3^(2/3) Gamma(2/3)^4 / (28 pi^2) chi^(2/3),
+// as exp(a chi^(-2/3)): ln(W / chi) = ln c - s/3 + a e^(-2s/3), with a taken
+// from the table's last node.
 // ---------------------------------------------------------------------------
+constexpr double kLnRadLimit = 0.378778931203860;    // ln(14 Gamma(2/3) / 3^(7/3))
+constexpr double kLnPairLimit = -0.968604787736293;  // ln(15 3^(2/3) Gamma(2/3)^4 / (28 pi^2))
+
+// ln(W / chi) (reduced as the table) at s > s_hi from its value l_hi at s_hi
+template <typename T>
+__device__ __forceinline__ T limit_continuation(T l_hi, T s_hi, T s, T ln_c) {
+  return ln_c - s * T(1.0 / 3.0) + (l_hi - ln_c + s_hi * T(1.0 / 3.0)) * exp(T(-2.0 / 3.0) * (s - s_hi));
+}
 __device__ __forceinline__ double cheb_clenshaw(const double* c, double x) {
   double b1 = 0.0, b2 = 0.0;
 #pragma unroll
@@ -76,7 +88,7 @@ __device__ __forceinline__ double rate_rad64(const RateView& r, double chi, doub
   if (s < r.s_lo)
     g = log(5.0 / (2.0 * kSqrt3)) + log1p(-(8.0 * kSqrt3 / 15.0) * chi);
   else if (s > s_hi)
-    g = cheb_g(r, s_hi) - (s - s_hi) * (1.0 / 3.0);
+    g = limit_continuation<double>(cheb_g(r, s_hi), s_hi, s, kLnRadLimit);
   else
     g = cheb_g(r, s);
   return kAlpha / gamma * chi * exp(g);
@@ -90,7 +102,7 @@ __device__ __forceinline__ double rate_pair64(const RateView& r, double chi, dou
   double lnf;  // ln(W eps / (alpha chi))
   if (s > s_hi) {
     const double chi_hi = exp(s_hi);
-    lnf = cheb_g(r, s_hi) - 8.0 / (3.0 * chi_hi) - (s - s_hi) * (1.0 / 3.0);
+    lnf = limit_continuation<double>(cheb_g(r, s_hi) - 8.0 / (3.0 * chi_hi), s_hi, s, kLnPairLimit);
   } else {
     lnf = cheb_g(r, s) - 8.0 / (3.0 * chi);
   }
@@ -120,7 +132,7 @@ __device__ __forceinline__ float rate_rad32_s(const float2* herm, int n, float s
     g = 0.3669845875401003f + log1pf(-0.9237604307034012f * chi);  // ln(5/(2 sqrt3)), 8 sqrt3/15
   } else if (t > (float)(n - 1)) {
     const float th = (float)(n - 1);
-    g = herm_g(herm, n, th) - (t - th) / (3.f * inv_h);
+    g = limit_continuation<float>(herm_g(herm, n, th), s0 + th / inv_h, s, (float)kLnRadLimit);
   } else {
     g = herm_g(herm, n, t);
   }
@@ -141,9 +153,11 @@ __device__ __forceinline__ float rate_pair32_s(const float2* herm, int n, float 
   const float t = (s - s0) * inv_h;
   if (t < 0.f) return 0.f;
   float g;
-  if (t > (float)(n - 1)) {
+  if (t > (float)(n - 1)) {  // the table holds ln(W eps/(alpha chi)) + 8/(3 chi)
     const float th = (float)(n - 1);
-    g = herm_g(herm, n, th) - (t - th) / (3.f * inv_h);
+    const float s_hi = s0 + th / inv_h;
+    const float l_hi = herm_g(herm, n, th) - 2.6666667f * expf(-s_hi);
+    g = limit_continuation<float>(l_hi, s_hi, s, (float)kLnPairLimit) + 2.6666667f / chi;
   } else {
     g = herm_g(herm, n, t);
   }

@@ -28,12 +28,19 @@ def cast_inputs(wl: synth.Workload, np_dtype):
     return out
 
 
-def run_gpu(sf, torch, tabs, wl, inputs, dtype, cap, cfg, seed=0, step_index=0, positions=False):
+def _x(positions, x0, s, n):
+    if not positions:
+        return None
+    return x0 if (x0 is not None and s == 0) else np.zeros((n, 3))
+
+
+def run_gpu(sf, torch, tabs, wl, inputs, dtype, cap, cfg, seed=0, step_index=0, positions=False, x0=None):
+    """x0: positions of the electrons (others start at 0) when positions are on."""
     main, fields, app = [], [], []
     for s, d in enumerate(inputs):
         n = d["id"].size
         main.append(sf.Store.from_arrays(d["p"], d["w"], d["tau"], d["id"], dtype=dtype, photon=s == 2,
-                                         capacity=max(n, 1), x=np.zeros((n, 3)) if positions else None))
+                                         capacity=max(n, 1), x=_x(positions, x0, s, n)))
         fields.append(sf.Fields.from_array(d["fields"] if d["fields"].shape[0] else np.zeros((1, 6)), dtype))
         app.append(sf.AppendBuffer(cap[s], dtype, positions=positions))
     rc, st = sf.step(tabs, main, fields, app, wl.dt, seed, step_index, cfg, check=False)
@@ -41,10 +48,12 @@ def run_gpu(sf, torch, tabs, wl, inputs, dtype, cap, cfg, seed=0, step_index=0, 
     return rc, st, main, fields, app
 
 
-def run_oracle(wl, inputs, cap, seed=0, step_index=0, **kw):
+def run_oracle(wl, inputs, cap, seed=0, step_index=0, x0=None, **kw):
     main, fields = [], []
-    for d in inputs:
-        main.append(oracle.Store.from_arrays(d["p"], d["w"], d["tau"], d["id"], capacity=max(d["id"].size, 1)))
+    for s, d in enumerate(inputs):
+        n = d["id"].size
+        main.append(oracle.Store.from_arrays(d["p"], d["w"], d["tau"], d["id"], capacity=max(n, 1),
+                                             x=_x(kw.get("positions", False), x0, s, n)))
         fields.append(d["fields"] if d["fields"].shape[0] else np.zeros((1, 6)))
     app = [oracle.Store(c) for c in cap]
     rc, st = oracle.step(main, fields, app, wl.dt, seed, step_index, **kw)

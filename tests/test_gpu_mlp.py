@@ -168,7 +168,9 @@ def test_sampler_fallback_and_inside():
     assert np.array_equal(d[out], dt[out]), "outside the trained range the table must sample"
     # inside: delta = sigmoid(10 y + ln chi) with y the network at the sampler's inputs
     r = (k.astype(np.float64) + 0.5) * 2.0**-32
-    X = net.features(chi.astype(np.float64), r)
+    c = net.cfg  # the network's inputs: x1 = ln(chi) f1_scale + f1_shift, x2 = logit(r) f2_scale
+    X = np.stack([np.log(chi.astype(np.float64)) * c.f1_scale + c.f1_shift,
+                  (np.log(r) - np.log1p(-r)) * c.f2_scale], axis=1)
     y = net.forward(torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
     z = 10.0 * y + np.log(chi.astype(np.float64))
     dref = 1.0 / (1.0 + np.exp(-z))

@@ -156,29 +156,69 @@ def test_cascade_fp32_parity(env):
     _check_cascade_fp32(env)
 
 
-def test_cascade_fp32_without_staging(env):
-    """FP32 emission tables too large for the write kernel's LDS staging area
-    beside them (70 x 320 CDF nodes, 94 KB): the write kernel falls back to
-    512-thread blocks that store each record directly, and the cascade must
-    agree with the oracle as on the staged path."""
+def test_cascade_fp32_without_staging(env, monkeypatch):
+    """FP32 emission tables too large for the direct write kernel's LDS staging
+    area beside them (70 x 320 CDF nodes, 94 KB), with the event log off: the
+    direct write kernel falls back to 512-thread blocks that store each record
+    directly, and the cascade must agree with the oracle as on the other
+    paths."""
     torch, sf, _ = env
-    _check_cascade_fp32((torch, sf, sf.Tables(sf.default_table_cfg(rad_cols=320))))
+    monkeypatch.setenv("SFQED_WRITE_REPLAY", "0")
+    _check_cascade_fp32((torch, sf, sf.Tables(sf.default_table_cfg(rad_cols=320))), stride=20_000,
+                        min_matched=20_000)
 
 
-def _check_cascade_fp32(env):
-    wl, st, ost, gmh, gah, om, oa = _cascade(env, "float32", 20_000)
+def _check_cascade_fp32(env, stride=4000, min_matched=100_000):
+    """FP32 crossed-field cascade (both processes, several generation rounds)
+    against the FP64 oracle on the same stream and the same FP32-rounded
+    inputs.  Every particle, input or appended, is matched by id (ids derive
+    from ancestry and the event counter).  A flip is a matched particle whose
+    event count differs from the oracle's; its later children exist on one
+    side only.  The flip fraction must be <= 1e-5 over >= 1e5 matched
+    particles, and every matched particle without a flip must agree element
+    by element: momentum, optical depth, birth time, alive flag."""
+    wl, st, ost, gmh, gah, om, oa = _cascade(env, "float32", stride)
     m = _match_all(gah, oa, gmh, om)
-    flips = tot = 0
+    flips = tot = unmatched = 0
+    ep, et, eb = [], [], []
     for s in range(3):
         ig, io, ng, no = m[s]
-        g_nev = np.concatenate([gmh[s]["nev"], gah[s]["nev"]])[ig]
-        o_nev = np.concatenate([om[s].nev[:om[s].count], oa[s].nev[:oa[s].count]])[io]
-        flips += int((g_nev != o_nev).sum())
+        cat_g = lambda k: np.concatenate([gmh[s][k], gah[s][k]])
+        cat_o = lambda a, b: np.concatenate([a, b])
+        g_nev, o_nev = cat_g("nev")[ig], cat_o(om[s].nev[:om[s].count], oa[s].nev[:oa[s].count])[io]
+        same = g_nev == o_nev
+        flips += int((~same).sum())
         tot += ig.size
-        print(f"  species {s}: gpu {ng} oracle {no} matched {ig.size}")
-    print(f"  flip fraction {flips / tot:.2e} ({flips} of {tot})")
-    assert flips / tot < 1e-3
-    assert abs(st.n_emit - ost.n_emit) <= 0.01 * ost.n_emit
+        unmatched += (ng - ig.size) + (no - io.size)
+        gp, op = cat_g("p")[ig][same], cat_o(om[s].p, oa[s].p)[io][same]
+        ep.append(np.linalg.norm(gp - op, axis=1) / np.linalg.norm(op, axis=1))
+        gt, ot = cat_g("tau")[ig][same], cat_o(om[s].tau, oa[s].tau)[io][same]
+        et.append(np.abs(gt - ot) / np.maximum(1.0, np.abs(ot)))
+        # birth times of appended particles (input particles start at 0)
+        na_g, na_o = gmh[s]["id"].size, om[s].count
+        app = (ig >= na_g)[same]
+        tg = gah[s]["t_birth"][ig[same][app] - na_g]
+        to = oa[s].t_birth[io[same][app] - na_o]
+        eb.append(np.abs(tg - to) / wl.dt)
+        if s == 2:
+            ga = cat_g("alive")[ig][same]
+            oa_ = cat_o(om[s].alive[:om[s].count], oa[s].alive[:oa[s].count])[io][same]
+            assert np.array_equal(ga != 0, oa_ != 0)
+        print(f"  species {s}: gpu {ng} oracle {no} matched {ig.size} flips {int((~same).sum())}")
+    ep, et, eb = np.concatenate(ep), np.concatenate(et), np.concatenate(eb)
+    q = lambda v: (np.median(v), np.quantile(v, 0.999), v.max())
+    print(f"  flip fraction {flips / tot:.2e} ({flips} of {tot}), unmatched {unmatched}")
+    print("  momentum rel err median/99.9%%/max %.1e %.1e %.1e" % q(ep))
+    print("  optical depth err median/99.9%%/max %.1e %.1e %.1e" % q(et))
+    print("  birth time err / dt median/99.9%%/max %.1e %.1e %.1e" % q(eb))
+    assert tot >= min_matched
+    assert flips <= max(1e-5 * tot, 1 if min_matched < 100_000 else 0)
+    assert flips > 0 or unmatched == 0
+    assert abs(st.n_emit - ost.n_emit) <= 1e-4 * ost.n_emit
+    # FP32 event-time arithmetic and FP32 tables (rates and samples to ~1e-6)
+    assert np.median(ep) < 1e-5 and ep.max() < 1e-2
+    assert np.median(et) < 1e-5 and et.max() < 1e-2
+    assert np.median(eb) < 1e-6 and eb.max() < 1e-3
 
 
 def test_push_fp64_parity(env):
@@ -199,6 +239,61 @@ def test_push_fp64_parity(env):
     print(f"  max rel err of pushed momenta {err.max():.2e}")
     assert err.max() < 1e-7
     assert (st.n_emit, st.n_pair) == (ost.n_emit, ost.n_pair)
+
+
+def test_push_fp32_parity(env):
+    """The Boris push between events in FP32 (one short step of the rotating
+    field with positions): event counts equal to the oracle's, momenta and
+    positions element by element."""
+    torch, sf, tabs = env
+    wl = synth.rotating_e(1_000_000, indices=np.arange(0, 1_000_000, 997), dt=300.0)
+    inp = cast_inputs(wl, np.float32)
+    n = inp[0]["id"].size
+    cap = [n * 20, n * 20, n * 100]
+    rng = np.random.default_rng(3)
+    x0 = rng.normal(0.0, 1e3, (n, 3)).astype(np.float32).astype(np.float64)
+    rc, st, gm, _, ga = run_gpu(sf, torch, tabs, wl, inp, torch.float32, cap, sf.step_cfg(push=True),
+                                positions=True, x0=x0)
+    assert rc == 0
+    orc_rc, ost, om, oa = run_oracle(wl, inp, cap, emission=1, pair=1, push=1, positions=True, x0=x0)
+    assert orc_rc == 0
+    g = gm[0].host()
+    flips = int((g["nev"] != om[0].nev[:n]).sum())
+    ok = g["nev"] == om[0].nev[:n]
+    ep = np.linalg.norm(g["p"][ok] - om[0].p[ok], axis=1) / np.linalg.norm(om[0].p[ok], axis=1)
+    ex = np.linalg.norm(g["x"][ok] - om[0].x[ok], axis=1) / np.maximum(np.linalg.norm(om[0].x[ok], axis=1), 1.0)
+    print(f"FP32 push: {n} electrons, flips {flips}, emitted gpu {st.n_emit} oracle {ost.n_emit}; momentum rel err "
+          f"median {np.median(ep):.1e} max {ep.max():.1e}; position rel err median {np.median(ex):.1e} "
+          f"max {ex.max():.1e}")
+    assert flips <= max(1, int(1e-5 * n))
+    assert np.median(ep) < 1e-6 and ep.max() < 1e-4
+    assert np.median(ex) < 1e-6 and ex.max() < 1e-4
+
+
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+def test_event_cap(env, dtype_name):
+    """max_events: a particle stops having events once it has had max_events
+    in the step and the step reports QED_ERR_EVENT_CAP, on both sides; the
+    capped counts and the children equal the oracle's."""
+    torch, sf, tabs = env
+    np_dtype = np.float32 if dtype_name == "float32" else np.float64
+    wl = synth.emission_static_b(100_000, indices=np.arange(0, 100_000, 97))
+    inp = cast_inputs(wl, np_dtype)
+    n = inp[0]["id"].size
+    cap = [1, 1, n * 40]
+    rc, st, gm, _, ga = run_gpu(sf, torch, tabs, wl, inp, getattr(torch, dtype_name), cap,
+                                sf.step_cfg(pair=False, push=False, max_events=3))
+    orc_rc, ost, om, oa = run_oracle(wl, inp, cap, emission=1, pair=0, push=0, max_events=3)
+    g = gm[0].host()
+    print(f"{dtype_name}: rc gpu {rc} oracle {orc_rc}; capped particles {int((g['nev'] == 3).sum())} of {n}; "
+          f"max events {st.max_events}")
+    assert rc == 5 and orc_rc == 5
+    assert st.max_events == 3 and g["nev"].max() == 3
+    same = g["nev"] == om[0].nev[:n]
+    assert same.mean() >= 1 - 1e-3
+    if dtype_name == "float64":
+        assert same.all()
+        assert np.array_equal(ga[2].host()["id"], oa[2].id[:oa[2].count])
 
 
 def test_merge_parity(env, orc):

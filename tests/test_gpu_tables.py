@@ -53,6 +53,27 @@ def test_rate_fp32_vs_oracle(env, orc):
         assert rel.max() <= 1e-5
 
 
+def test_rate_above_the_tables_vs_oracle(env, orc):
+    """Above rate_chi_max both rates follow their chi^(2/3) limits as
+    exp(a chi^(-2/3)), a matched at the table's last node: within 2e-7 of the
+    oracle (FP64 path) and 1e-5 (FP32 path) up to chi = 1e10."""
+    torch, sf, tabs = env
+    rng = np.random.default_rng(2)
+    for proc, fn in ((0, orc.rate_rad_reduced_many), (1, orc.rate_pair_reduced_many)):
+        chi = np.concatenate([_lu(rng, 1.5e5, 1e10, 400), [1.5e5, 1e6, 1e8, 1e10]])
+        e = np.full_like(chi, 1e4)
+        ref = ALPHA / e * fn(chi)
+        got = sf.eval_rate(tabs, proc, torch.tensor(chi, device="cuda"), torch.tensor(e, device="cuda")).cpu().numpy()
+        rel64 = np.abs(got / ref - 1)
+        c32, e32 = chi.astype(np.float32), e.astype(np.float32)
+        g32 = sf.eval_rate(tabs, proc, torch.tensor(c32, device="cuda"), torch.tensor(e32, device="cuda")).cpu().numpy()
+        ref32 = ALPHA / e32.astype(np.float64) * fn(c32.astype(np.float64))
+        rel32 = np.abs(g32.astype(np.float64) / ref32 - 1)
+        print(f"process {proc} above the table: FP64 max rel err {rel64.max():.2e}, FP32 {rel32.max():.2e}")
+        assert rel64.max() <= 2e-7
+        assert rel32.max() <= 1e-5
+
+
 def _sample_errors(got, ref_v, ref_omv):
     g = got.astype(np.float64)
     e1 = np.abs(g - ref_v) / ref_v

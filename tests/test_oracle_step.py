@@ -221,3 +221,25 @@ def test_init_tau_reserved_counter(orc):
     ref = -np.log((blocks[:, 0].astype(np.float64) + 0.5) * 2.0 ** -32)
     np.testing.assert_array_equal(s.tau[[0, 2, 3]], ref[[0, 2, 3]])
     np.testing.assert_array_equal(s.tau[[1, 4]], [2.0, 0.5])
+
+
+# ----------------------------------------------------------------------------- event cap
+def test_event_cap(orc):
+    """max_events: once a particle has had max_events events in the step it has
+    no more (its rate is taken as zero), and the step reports it (status 5).
+    The first events are those of the uncapped step (same draws), so the
+    capped counts are min(uncapped, cap) and the children are the first ones
+    of each parent in the uncapped step."""
+    wl = synth.emission_static_b(100_000, indices=np.arange(0, 100_000, 500))
+    runs = []
+    for cap in (1 << 20, 3):
+        main, fields, app = _stores(orc, wl)
+        rc, stats = orc.step(main, fields, app, wl.dt, 0, 0, emission=1, pair=0, push=0, max_events=cap)
+        runs.append((rc, stats, main[0].nev[:main[0].count].copy(), app[2]))
+    (rc_f, st_f, nev_f, app_f), (rc_c, st_c, nev_c, app_c) = runs
+    assert rc_f == 0 and rc_c == 5 and st_c.capped == 1
+    assert nev_f.max() > 3
+    np.testing.assert_array_equal(nev_c, np.minimum(nev_f, 3))
+    first = np.concatenate([np.arange(o, o + k) for o, k in zip(np.r_[0, np.cumsum(nev_f)[:-1]], nev_c)])
+    np.testing.assert_array_equal(app_c.id[:app_c.count], app_f.id[first])
+    np.testing.assert_array_equal(app_c.p, app_f.p[first])
