@@ -187,6 +187,7 @@ typedef struct {
   int64_t max_events;           /* per particle and step; reaching it is an error */
   int32_t profile;              /* 1: time every launch with HIP events into stats */
   int32_t nev;                  /* 1: write event counts (nev) of appended particles */
+  int32_t validate;             /* 1: run qed_validate first; on QED_ERR_ARG nothing is changed */
 } qed_step_cfg;
 
 void qed_step_cfg_default(qed_step_cfg *cfg);
@@ -228,6 +229,18 @@ qed_status qed_init_tau(qed_ensemble *ens, uint64_t seed, uint32_t step, void *s
  * ensemble is then partly advanced and the caller restores it. */
 qed_status qed_step(const qed_tables *tab, const qed_step_cfg *cfg, qed_ensemble *ens, qed_append app[3],
                     double dt, uint64_t seed, uint32_t step, qed_step_stats *stats, void *stream);
+
+/* Debug validation pass.  Counts, per species, the live particles (index <
+ * count) whose momentum, position (when present), weight or optical depth, or
+ * whose six field components (the particle's own, or the shared value when
+ * stride = 0), are not finite: a NaN or an infinity there does not stop the
+ * step but spreads through chi and the rates into every child of the
+ * particle.  bad (may be NULL) receives the three counts.  Returns QED_ERR_ARG
+ * when any count is non-zero (qed_last_error names them), QED_OK otherwise.
+ * It reads each live particle once and waits for `stream` (one small
+ * device-to-host copy); qed_step_cfg.validate = 1 runs it at the start of
+ * qed_step and qed_step_merged, before anything is changed. */
+qed_status qed_validate(const qed_ensemble *ens, int64_t bad[3], void *stream);
 
 /* Merge (the merge of per-thread arrays of Sec. 4.2): drops photons with
  * alive = 0 from `ens` (stable), then appends the surviving particles of

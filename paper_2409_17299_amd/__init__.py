@@ -68,7 +68,8 @@ class CEnsemble(C.Structure):
 
 class StepCfg(C.Structure):
     _fields_ = [("emission", C.c_int32), ("pair", C.c_int32), ("push", C.c_int32), ("gamma_min", C.c_double),
-                ("max_events", C.c_int64), ("profile", C.c_int32), ("nev", C.c_int32)]
+                ("max_events", C.c_int64), ("profile", C.c_int32), ("nev", C.c_int32),
+                ("validate", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -155,6 +156,7 @@ def lib():
                                    C.c_uint64, C.c_uint32, C.POINTER(StepStats), v]),
             "qed_merge": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CAppend), v]),
             "qed_merge_noalloc": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(CAppend), v]),
+            "qed_validate": (C.c_int, [C.POINTER(CEnsemble), C.POINTER(C.c_int64), v]),
             "qed_step_merged": (C.c_int, [v, C.POINTER(StepCfg), C.POINTER(CEnsemble), C.POINTER(CAppend),
                                           C.c_double, C.c_uint64, C.c_uint32, C.POINTER(StepStats), v]),
             "qed_resample_cfg_default": (None, [C.POINTER(ResampleCfg)]),
@@ -426,12 +428,13 @@ def _ensemble(main: list, fields: list) -> CEnsemble:
 
 
 def step_cfg(emission=True, pair=True, push=True, gamma_min=1.0, max_events=1 << 20, profile=False,
-             nev=True) -> StepCfg:
+             nev=True, validate=False) -> StepCfg:
     cfg = StepCfg()
     lib().qed_step_cfg_default(C.byref(cfg))
     cfg.emission, cfg.pair, cfg.push = int(emission), int(pair), int(push)
     cfg.gamma_min, cfg.max_events, cfg.profile = float(gamma_min), int(max_events), int(profile)
     cfg.nev = int(nev)
+    cfg.validate = int(validate)
     return cfg
 
 
@@ -476,6 +479,14 @@ def step_merged(tables: Tables, main: list, fields: list, app: list, dt: float, 
     if check:
         _check(rc)
     return rc, st
+
+
+def validate(main: list, fields: list, stream=None) -> tuple[int, list[int]]:
+    """qed_validate: (status, particles with non-finite values per species)."""
+    e = _ensemble(main, fields)
+    bad = (C.c_int64 * 3)()
+    rc = lib().qed_validate(C.byref(e), bad, _stream(stream))
+    return rc, [int(b) for b in bad]
 
 
 def merge(main: list, fields: list, app: list, stream=None, noalloc: bool = False):

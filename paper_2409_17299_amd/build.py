@@ -9,7 +9,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 SOURCES = ["csrc/tables.hip", "csrc/step.hip", "csrc/grid.hip", "csrc/mlp.hip", "csrc/api.cpp", "csrc/mlp_api.cpp",
-           "csrc/noalloc.hip"]
+           "csrc/noalloc.hip", "csrc/validate.hip"]
 LIB = PKG / "libsfqed.so"
 
 

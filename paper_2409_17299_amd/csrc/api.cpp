@@ -34,6 +34,7 @@ constexpr int kAliveCount = kSlots + 4;
 constexpr int kStats = kSlots + 8;      // 8 words
 constexpr int kResampleCount = kSlots + 16;  // 3 words: survivors of each species' compaction
 constexpr int kMergedCursor = kSlots + 24;   // photons in the main arrays so far (qed_step_merged)
+constexpr int kNonFinite = kSlots + 32;      // 3 words: particles with non-finite values (qed_validate)
 
 // Library-owned scratch of one device: per-particle counts, offsets and event
 // list of the largest launch so far, look-back words, and a control block.
@@ -524,6 +525,29 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   return QED_OK;
 }
 
+// The validation pass: per species, live particles with a non-finite
+// momentum, position, weight, optical depth or field component.  Blocking
+// (one small device-to-host copy).
+template <typename T>
+qed_status validate_impl(Scratch* S, const qed_ensemble* ens, int64_t bad[3], hipStream_t st) {
+  auto* cnt = reinterpret_cast<unsigned long long*>(S->ctrl + kNonFinite);
+  SFQED_HIP(hipMemsetAsync(cnt, 0, 3 * sizeof(uint64_t), st));
+  for (int s = 0; s < 3; ++s) {
+    const int64_t n = ens->s[s].count;
+    SFQED_HIP(launch_count_nonfinite<T>(view_of<T>(ens->s[s]), fields_of<T>(ens->f[s], n), n, cnt + s, st));
+  }
+  uint64_t h[3];
+  SFQED_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+  SFQED_HIP(hipStreamSynchronize(st));
+  for (int s = 0; s < 3; ++s) bad[s] = (int64_t)h[s];
+  if (h[0] || h[1] || h[2]) {
+    set_error("non-finite values in " + std::to_string(h[0]) + " electrons, " + std::to_string(h[1]) +
+              " positrons, " + std::to_string(h[2]) + " photons");
+    return QED_ERR_ARG;
+  }
+  return QED_OK;
+}
+
 template <typename T>
 qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble* ens, qed_append* app,
                      double dt, uint64_t seed, uint32_t step, qed_step_stats* stats, hipStream_t st,
@@ -534,6 +558,11 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
     return QED_ERR_HIP;
   }
   std::lock_guard<std::mutex> lk(S->mu);
+  if (cfg->validate) {  // before anything is changed
+    int64_t bad[3];
+    const qed_status v = validate_impl<T>(S, ens, bad, st);
+    if (v != QED_OK) return v;
+  }
   SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t) * kCtrlWords, st));
   int slot = 0;
   const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
@@ -1015,6 +1044,7 @@ void qed_step_cfg_default(qed_step_cfg* c) {
   c->max_events = 1 << 20;
   c->profile = 0;
   c->nev = 1;
+  c->validate = 0;
 }
 
 qed_status qed_init_tau(qed_ensemble* ens, uint64_t seed, uint32_t step, void* stream) {
@@ -1075,6 +1105,33 @@ qed_status qed_step_merged(const qed_tables* tab, const qed_step_cfg* cfg, qed_e
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (ens->dtype == QED_F32) return step_impl<float>(tab, cfg, ens, app, dt, seed, step, stats, st, true);
   return step_impl<double>(tab, cfg, ens, app, dt, seed, step, stats, st, true);
+}
+
+qed_status qed_validate(const qed_ensemble* ens, int64_t bad[3], void* stream) {
+  if (!ens || (ens->dtype != QED_F32 && ens->dtype != QED_F64)) {
+    set_error("null ensemble or bad dtype");
+    return QED_ERR_ARG;
+  }
+  const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
+  for (int s = 0; s < 3; ++s) {
+    if (!species_ok(ens->s[s], s == 2, positions) || !fields_ok(ens->f[s], ens->s[s].count)) {
+      set_error("invalid species " + std::to_string(s));
+      return QED_ERR_ARG;
+    }
+  }
+  Scratch* S = scratch_for_current_device();
+  if (!S) {
+    set_error("no HIP device");
+    return QED_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  int64_t local[3];
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const qed_status rc = ens->dtype == QED_F32 ? validate_impl<float>(S, ens, local, st)
+                                              : validate_impl<double>(S, ens, local, st);
+  if (bad)
+    for (int s = 0; s < 3; ++s) bad[s] = rc == QED_ERR_HIP ? 0 : local[s];
+  return rc;
 }
 
 qed_status qed_merge(qed_ensemble* ens, const qed_append app[3], void* stream) {

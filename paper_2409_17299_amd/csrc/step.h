@@ -214,6 +214,11 @@ hipError_t launch_count_alive_rec(const Rec<T>* rec, int64_t n, unsigned long lo
 template <typename T>
 hipError_t launch_append_records(const SpeciesView<T>& dst, int64_t at, const Rec<T>* rec, const T* pos, int64_t n,
                                  int positions, hipStream_t st);
+// particles of [0, n) with a non-finite momentum, position, weight, optical
+// depth or field component are added to *bad (validate.hip)
+template <typename T>
+hipError_t launch_count_nonfinite(const SpeciesView<T>& s, const FieldView<T>& f, int64_t n,
+                                  unsigned long long* bad, hipStream_t st);
 template <typename T>
 hipError_t launch_init_tau(double* tau, const uint64_t* id, int64_t n, uint64_t seed, uint32_t step, hipStream_t st);
 template <typename T>

@@ -55,6 +55,9 @@ def test_argument_errors_without_device(L):
     # null handles and bad configurations are rejected before any HIP call
     assert L.qed_step(None, None, None, None, 1.0, 0, 0, None, None) == 1
     assert L.qed_merge(None, None, None) == 1
+    assert L.qed_validate(None, None, None) == 1
+    c = sf.step_cfg()
+    assert c.validate == 0 and sf.step_cfg(validate=True).validate == 1
     assert L.qed_mlp_create(None, None) == 1
     bad = sf.mlp_cfg(chi_min=-1.0)
     h = C.c_void_p()
