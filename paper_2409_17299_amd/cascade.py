@@ -22,7 +22,7 @@ from . import (AppendBuffer, Fields, Store, field_buffers, gather_fields, merge,
 
 
 def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_capacity, dtype=None, seed: int = 0,
-        cfg=None, on_step=None, stream=None, resample=None, grid=None, merged=True):
+        cfg=None, on_step=None, stream=None, resample=None, grid=None, merged=True, start: int = 0, main=None):
     """species: [(p [n, 3], w [n], tau [n], id [n])] or, with positions,
     [(p, w, tau, id, x [n, 3])] for e-, e+, photons;
     field_of_step(k): the [1, 6] field (ex ey ez bx by bz) shared by all
@@ -32,20 +32,26 @@ def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_cap
     resample: None, or the keyword arguments of resample_cfg
     (photon_energy_min, target) applied after every merge, with the cascade's
     seed and the step index; merged: one qed_step_merged call per step (else
-    qed_step then qed_merge; the results are identical).  Returns (counts
+    qed_step then qed_merge; the results are identical); start: index of the
+    first global step (a run restored from a checkpoint saved after step
+    start - 1 continues with start); main: device stores to continue from
+    (checkpoint.load gives them; species, capacity and dtype are then taken
+    from them).  Returns (counts
     [steps + 1, 3], per-step stats, seconds per step, the final device stores,
     total weight [steps + 1, 3])."""
     import torch
-    dtype = dtype or torch.float32
-    positions = len(species[0]) > 4
+    dtype = main[0].dtype if main is not None else (dtype or torch.float32)
+    positions = main[0].x is not None if main is not None else len(species[0]) > 4
     if grid is not None and not positions:
         raise ValueError("fields on a grid need particle positions")
     cfg = cfg if cfg is not None else step_cfg(push=True, nev=False)
-    main = [Store.from_arrays(sp[0], sp[1], sp[2], sp[3], dtype=dtype, photon=s == 2, capacity=capacity[s],
-                              x=sp[4] if positions else None)
-            for s, sp in enumerate(species)]
-    for m in main:
-        m.nev = None
+    if main is None:
+        main = [Store.from_arrays(sp[0], sp[1], sp[2], sp[3], dtype=dtype, photon=s == 2, capacity=capacity[s],
+                                  x=sp[4] if positions else None)
+                for s, sp in enumerate(species)]
+        for m in main:
+            m.nev = None
+    capacity = [m.capacity for m in main]
     app = [AppendBuffer(app_capacity[s], dtype, positions=positions) for s in range(3)]
     fbuf = [field_buffers(capacity[s], dtype) for s in range(3)] if grid is not None else None
     def weight():
@@ -54,7 +60,7 @@ def run(tables, species, dt: float, steps: int, field_of_step, capacity, app_cap
     counts = [[m.count for m in main]]
     weights = [weight()]
     stats, secs = [], []
-    for k in range(steps):
+    for k in range(start, start + steps):
         t0 = time.perf_counter()
         if grid is not None:
             g, box, fill = grid
