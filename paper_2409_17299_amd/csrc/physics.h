@@ -20,6 +20,29 @@ __device__ __forceinline__ T chi_of(const T p[3], T e, const T E[3], const T B[3
   return c2 > T(0) ? sqrt(c2) : T(0);
 }
 
+// A photon's energy |k| and chi, and whether it can produce a pair (|k| >= 2).
+// Below chi ~ 0.1 the pair rate goes as exp(-8/(3 chi)) and so multiplies a
+// relative error of chi by about 8/(3 chi) (some 70 at the smallest chi whose
+// rate exceeds 1e-30): the FP32 path evaluates |k| and chi from its FP32
+// inputs in FP64 (full-rate enough on this chip for one evaluation per
+// photon and trip) and rounds each once, which puts chi within half an ulp,
+// and takes the threshold decision in FP64.  Leptons keep FP32 chi: their
+// emission rate varies no faster than chi.
+template <typename T>
+__device__ __forceinline__ bool photon_chi(const T p[3], const T E[3], const T B[3], T& eps, T& chi) {
+  if constexpr (sizeof(T) == 4) {
+    const double pd[3] = {p[0], p[1], p[2]}, Ed[3] = {E[0], E[1], E[2]}, Bd[3] = {B[0], B[1], B[2]};
+    const double e = sqrt(pd[0] * pd[0] + pd[1] * pd[1] + pd[2] * pd[2]);
+    eps = (float)e;
+    chi = (float)chi_of<double>(pd, e, Ed, Bd);
+    return e >= 2.0;
+  } else {
+    eps = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    chi = chi_of<double>(p, eps, E, B);
+    return eps >= 2.0;
+  }
+}
+
 // Boris scheme over h for charge q: half electric kick, rotation in B about
 // the mid-step Lorentz factor, half electric kick.
 template <typename T>

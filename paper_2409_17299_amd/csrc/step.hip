@@ -542,11 +542,11 @@ __device__ __forceinline__ bool photon_iter(const StepArgs<T>& a, const LdsTable
                                             int64_t out_base) {
   const T dtT = (T)a.dt;
   if (!(L.t < dtT)) return true;
-  const T eps = sqrt(L.p[0] * L.p[0] + L.p[1] * L.p[1] + L.p[2] * L.p[2]);
+  T eps, chi0;
+  const bool can_pair = photon_chi<T>(L.p, L.E, L.B, eps, chi0);
   T W = T(0);
-  const T chi0 = chi_of<T>(L.p, eps, L.E, L.B);
   const T s0 = log_chi<T>(chi0);
-  if (a.pair && eps >= T(2)) W = rate_of<T>(a, lt, 1, chi0, s0, eps);
+  if (a.pair && can_pair) W = rate_of<T>(a, lt, 1, chi0, s0, eps);
   const T rem = dtT - L.t;
   const double X = (double)W * (double)rem;
   const T inv_eps = eps > T(0) ? T(1) / eps : T(0);
@@ -1635,16 +1635,21 @@ __global__ void k_eval_particles(TableView tab, int species, const T* px, const 
   const T p[3] = {px[i], py[i], pz[i]};
   const int64_t o = f.stride ? i : 0;
   const T E[3] = {f.ex[o], f.ey[o], f.ez[o]}, B[3] = {f.bx[o], f.by[o], f.bz[o]};
-  const T pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-  const T e = species == 2 ? sqrt(pp) : sqrt(T(1) + pp);
-  const T chi = chi_of<T>(p, e, E, B);
+  T e, chi;
+  bool can_pair = false;
+  if (species == 2) {
+    can_pair = photon_chi<T>(p, E, B, e, chi);
+  } else {
+    e = sqrt(T(1) + p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    chi = chi_of<T>(p, e, E, B);
+  }
   T w;
   if constexpr (sizeof(T) == 4) {
     const RateView& r = tab.rate[species == 2 ? 1 : 0];
-    w = species == 2 ? (e >= 2.f ? rate_pair32(r.herm, r.n, r.hs_lo, r.inv_h, chi, e) : 0.f)
+    w = species == 2 ? (can_pair ? rate_pair32(r.herm, r.n, r.hs_lo, r.inv_h, chi, e) : 0.f)
                      : rate_rad32(r.herm, r.n, r.hs_lo, r.inv_h, chi, e);
   } else {
-    w = species == 2 ? (e >= 2.0 ? rate_pair64(tab.rate[1], chi, e) : 0.0) : rate_rad64(tab.rate[0], chi, e);
+    w = species == 2 ? (can_pair ? rate_pair64(tab.rate[1], chi, e) : 0.0) : rate_rad64(tab.rate[0], chi, e);
   }
   if (chi_out) chi_out[i] = chi;
   if (w_out) w_out[i] = w;

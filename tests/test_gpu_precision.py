@@ -3,10 +3,14 @@ static B field; every 1000th particle of each species here, regenerated
 exactly by index): the FP64 GPU path, the FP32 table path and the BF16
 surrogate against the FP64 oracle, on one shared stream of 32-bit uniforms.
 
-* chi: FP64 within 1e-13, FP32 within 2e-6 of the oracle's chi at the same
-  rounded inputs; rates at the path's own chi: FP64 <= 1e-12 relative, FP32
-  <= 1e-5 relative (where the rate exceeds 1e-30; pair rates below chi ~ 0.04
-  are smaller);
+* chi: FP64 within 1e-13 of the oracle's chi at the same rounded inputs;
+  FP32 leptons within 2e-6, FP32 photons (chi evaluated in FP64 and rounded
+  once) within half an ulp, 2^-24;
+* rates (where the rate exceeds 1e-30; pair rates below chi ~ 0.04 are
+  smaller), FP64 <= 1e-12 and FP32 <= 1e-5 relative, both at the path's own
+  chi and end to end: the path's rate against the oracle's rate at the
+  oracle's chi of the same inputs (for pairs the FP32 chi rounding enters
+  amplified by up to 8/(3 chi) ~ 70);
 * first-event energy fraction at the particle's chi: FP64 table within 1e-7,
   FP32 table within 5e-5 (at the chi of the FP32-rounded inputs);
 * surrogate (emission, trained range [1e-2, 1e2]): per-draw |d ln delta|
@@ -58,7 +62,9 @@ def test_rates(sweep, s):
     turns a chi error of a few FP32 ulp into 2e-5 by its e^(-8/(3 chi)) factor)."""
     torch, sf, tabs, wl = sweep
     sp = wl.species[s]
-    for dt, np_dt, tol_chi, tol in ((torch.float64, np.float64, 1e-13, 1e-12), (torch.float32, np.float32, 2e-6, 1e-5)):
+    half_ulp = 2.0 ** -24
+    for dt, np_dt, tol_chi, tol in ((torch.float64, np.float64, 1e-13, 1e-12),
+                                    (torch.float32, np.float32, half_ulp * (1 + 1e-9) if s == 2 else 2e-6, 1e-5)):
         chi_o, e = oracle_chi(sp, s == 2, np_dt)
         st = sf.Store.from_arrays(sp.p, sp.w, sp.tau, sp.id, dtype=dt, photon=s == 2)
         chi_g, w_g = sf.eval_particles(tabs, s, st, sf.Fields.from_array(sp.fields, dt))
@@ -73,9 +79,14 @@ def test_rates(sweep, s):
         ok = (w_o > floor) & (w_g > floor)
         assert (w_g[w_o == 0] == 0).all()
         rel = np.abs(w_g[ok] - w_o[ok]) / w_o[ok]
-        print(f"species {s} {dt}: chi max rel err {ce.max():.1e}; {ok.sum()} rates, max rel err {rel.max():.2e}, "
-              f"median {np.median(rel):.2e}")
+        w_e2e = oracle_rates_at(chi_o, e, s)  # the oracle's rate at its own chi
+        ok2 = (w_e2e > floor) & (w_g > floor)
+        rel2 = np.abs(w_g[ok2] - w_e2e[ok2]) / w_e2e[ok2]
+        worst = int(np.argmax(np.where(ok2, np.abs(w_g - w_e2e) / np.where(ok2, w_e2e, 1.0), 0.0)))
+        print(f"species {s} {dt}: chi max rel err {ce.max():.2e}; {ok.sum()} rates, max rel err {rel.max():.2e}, "
+              f"median {np.median(rel):.2e}; end to end max {rel2.max():.2e} (at chi {chi_o[worst]:.3g})")
         assert rel.max() <= tol, rel.max()
+        assert rel2.max() <= tol, rel2.max()
         assert ok.sum() > 0.3 * sp.n
 
 
