@@ -4,18 +4,21 @@
 // Per wave of the count launch, a sequence of records in blocks of kLogBlock
 // bytes.  A record has a fixed size, so that the reader can fetch the next
 // record before it has read the current one:
-//   header, 16 bytes: m_new (64-bit mask of the lanes that took a new particle
-//     with an event on this trip) and m_ev (lanes with an event);
+//   header, 32 bytes: m_fresh (64-bit mask of the lanes that took a new
+//     particle on this trip, with or without an event), m_ev (lanes with an
+//     event), base (the launch index of the particle the lowest fresh lane
+//     took) and tag (kLogRecord);
 //   64 slots of `slot` bytes, slot l for lane l, written only for lanes with
-//     an event (the event's values and the particle's launch index) or whose
+//     an event (the event's sampled value z and its sub-interval h) or whose
 //     particle, which had events, finished on this trip (its final optical
 //     depth).
+// The wave queue serves a trip's fresh lanes from one contiguous range, in
+// lane order, so fresh lane l took particle base + (fresh lanes below l).  A
+// fresh lane whose particle has no event at all finishes on that trip and is
+// never replayed, but it still takes a particle: it counts in that rank.
 // A block holds log_records_per_block records; the last position of a block
-// is kept for a marker.  A new lane always has an event on its first logged
-// trip, so m_new is a subset of m_ev in every record.  Markers are the
-// headers that break that rule: (~0, 0) ends the wave's log, (~0, 1) moves
-// to the block whose offset is the first 8 bytes of slot 0.  (A record may
-// have m_new = ~0: every lane took a new particle, and then m_ev = ~0 too.)
+// is kept for a marker, a header whose tag is kLogEnd (the wave's log ends)
+// or kLogJump (the log goes on in the block at offset `base`).
 #pragma once
 
 #include <stdint.h>
@@ -29,14 +32,22 @@
 namespace sfqed {
 
 constexpr uint64_t kLogBlock = 128 * 1024;
-constexpr uint64_t kLogMarkNew = ~0ull;
-constexpr uint64_t kLogMarkEnd = 0;   // m_ev of the end marker
-constexpr uint64_t kLogMarkJump = 1;  // m_ev of the jump marker
+constexpr uint64_t kLogHeader = 32;
+constexpr uint64_t kLogRecord = 0;  // tags
+constexpr uint64_t kLogEnd = 1;
+constexpr uint64_t kLogJump = 2;
 
-SFQED_HD constexpr uint64_t log_record_bytes(uint32_t slot) { return 16ull + 64ull * slot; }
+SFQED_HD constexpr uint64_t log_record_bytes(uint32_t slot) { return kLogHeader + 64ull * slot; }
 SFQED_HD constexpr uint64_t log_records_per_block(uint32_t slot) { return kLogBlock / log_record_bytes(slot); }
 
-// a marker, not a record: some new lane without an event
-SFQED_HD inline bool log_is_marker(uint64_t m_new, uint64_t m_ev) { return (m_new & ~m_ev) != 0; }
+// the launch index of fresh lane `lane` of a record
+SFQED_HD inline uint64_t log_fresh_index(uint64_t m_fresh, uint64_t base, int lane) {
+  const uint64_t below = lane == 0 ? 0ull : (m_fresh & (~0ull >> (64 - lane)));
+#if defined(__HIP_DEVICE_COMPILE__)
+  return base + (uint64_t)__popcll(below);
+#else
+  return base + (uint64_t)__builtin_popcountll(below);
+#endif
+}
 
 }  // namespace sfqed

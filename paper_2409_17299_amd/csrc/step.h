@@ -60,12 +60,11 @@ constexpr int kStatReruns = 7;          // lepton launches written by the direct
 // from one pool; log_ctl words of the launch: blocks handed out, overflow
 // flag, bytes the launch needed.
 constexpr int kLogUsed = 0, kLogOverflow = 1, kLogNeed = 2;
-// bytes of one lane's slot: an event's z and h in the step's dtype, the
-// uniform draw of its child's optical depth (32 bits) and the particle's
-// launch index, or a finished particle's optical depth (FP64)
+// bytes of one lane's slot: an event's z and h in the step's dtype, or a
+// finished particle's optical depth (FP64)
 template <typename T>
 constexpr uint32_t log_slot_bytes() {
-  return sizeof(T) == 4 ? 16u : 32u;
+  return 2u * (uint32_t)sizeof(T);
 }
 
 // A launch covers up to two source ranges ("parts"): electrons and positrons

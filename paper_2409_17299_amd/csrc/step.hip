@@ -20,6 +20,8 @@
 // The append order therefore is: particles in index order, children of one
 // particle in event order -- the same for every run and every grid size.
 
+#include <type_traits>
+
 #include "lib.h"
 #include "line_rule.h"
 #include "physics.h"
@@ -170,7 +172,6 @@ struct Lane {
   bool capped;
   bool changed;  // state differs from what was loaded
   T lz, lh;      // the last event's sampler value z and sub-interval h (logged by the count pass)
-  uint32_t lu;   // the last event's draw for the child's optical depth (logged)
 };
 
 // E and B of the particle's root (children keep the fields of the particle
@@ -465,7 +466,7 @@ __device__ __forceinline__ void write_child(Rec<T>* out, T* pos, int64_t idx, co
 
 // One sub-cycle of Algorithm 1 for a lepton.  Returns true when the particle
 // has reached the end of the step.  kLog keeps what the write pass needs to
-// replay an event in L.lz, L.lh and L.lu.
+// replay an event in L.lz and L.lh.
 template <typename T, bool kWrite, bool kLog = false>
 __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTables& lt, Lane<T>& L, T q,
                                             int64_t out_base, Outbox<T>& O) {
@@ -502,7 +503,6 @@ __device__ __forceinline__ bool lepton_iter(const StepArgs<T>& a, const LdsTable
   if constexpr (kLog) {
     L.lz = z;
     L.lh = h;
-    L.lu = u.z;
   }
   if (kWrite) {
     const int64_t o = out_base + L.j;
@@ -637,6 +637,10 @@ __device__ __forceinline__ void wq_init(WaveQueue& q) {
 
 // Returns the item index of this lane (>= n: none) for lanes with need set.
 // ctr: kQueueParts counters, kQueueStride words apart, zero at launch.
+// kOneChunk: serve the lanes from one contiguous range only (lanes left over
+// wait for the next call), so that the lanes served get consecutive items in
+// lane order -- what the event log's records assume.
+template <bool kOneChunk = false>
 __device__ __forceinline__ uint64_t wq_take(WaveQueue& q, bool need, uint64_t n, unsigned long long* ctr,
                                             uint32_t waves) {
   uint64_t m = __ballot(need);
@@ -682,6 +686,7 @@ __device__ __forceinline__ uint64_t wq_take(WaveQueue& q, bool need, uint64_t n,
     }
     m &= ~served;
     q.next += take;
+    if constexpr (kOneChunk) break;
   }
   return got;
 }
@@ -690,14 +695,14 @@ __device__ __forceinline__ uint64_t wq_take(WaveQueue& q, bool need, uint64_t n,
 // With the log on, the lepton count pass records what the write pass needs
 // to replay each event without the tables (format in event_log.h): per trip
 // of a wave in which some lane had an event, or finished a particle that had
-// one, a record of the lanes that took a new particle and of the lanes with
-// an event, and per such lane a slot: the event's sampler value
-// z = logit(delta), sub-interval h, the uniform draw of the child's optical
-// depth and the particle's launch index, or the finished particle's optical
-// depth.  A particle without events is never logged.  When the pool runs out, the wave stops writing, raises
-// the overflow flag and the direct write kernel does the launch's writes;
-// every wave still adds up the bytes it would have needed, so that the host
-// can grow the pool.
+// one, a record of the lanes that took a new particle (and the launch index
+// the first of them took) and of the lanes with an event, and per such lane
+// a slot: the event's sampler value z = logit(delta) and sub-interval h, or
+// the finished particle's optical depth.  A particle without events is never
+// replayed.  When the pool runs out, the wave stops writing, raises the
+// overflow flag and the direct write kernel does the launch's writes; every
+// wave still adds up the bytes it would have needed, so that the host can
+// grow the pool.
 // Wave-uniform state of one wave's log, kept in 32-bit words (scalar
 // registers are scarce in the count kernel).
 struct LogWriter {
@@ -707,35 +712,36 @@ struct LogWriter {
   uint32_t state; // 0: no block yet, 1: writing, 2: the pool ran out
 };
 
-// A lane's slot of a record (FP32: one 16-byte piece; FP64: two).
+// A lane's slot of a record (FP32: 8 bytes; FP64: 16).
 template <typename T>
-struct LogSlot {
-  uint4 c[log_slot_bytes<T>() / 16];
-};
+using LogSlot = typename std::conditional<sizeof(T) == 4, uint2, uint4>::type;
 
 template <typename T>
-__device__ __forceinline__ LogSlot<T> log_event_slot(T z, T h, uint32_t u, int64_t k) {
-  LogSlot<T> s;
+__device__ __forceinline__ LogSlot<T> log_event_slot(T z, T h) {
   if constexpr (sizeof(T) == 4) {
-    s.c[0] = make_uint4(fbits(z), fbits(h), u, (uint32_t)k);
+    return make_uint2(fbits(z), fbits(h));
   } else {
     const uint64_t zb = __builtin_bit_cast(uint64_t, z), hb = __builtin_bit_cast(uint64_t, h);
-    const uint64_t kb = (uint64_t)k;
-    s.c[0] = make_uint4(lo32(zb), hi32(zb), lo32(hb), hi32(hb));
-    s.c[1] = make_uint4(u, 0u, lo32(kb), hi32(kb));
+    return make_uint4(lo32(zb), hi32(zb), lo32(hb), hi32(hb));
   }
-  return s;
 }
 
 template <typename T>
 __device__ __forceinline__ LogSlot<T> log_final_slot(double tau) {
-  LogSlot<T> s;
-  const uint64_t t = __builtin_bit_cast(uint64_t, tau);
-  s.c[0] = make_uint4(lo32(t), hi32(t), 0u, 0u);
-  if constexpr (sizeof(T) == 8) s.c[1] = make_uint4(0u, 0u, 0u, 0u);
-  return s;
+  const uint64_t b = __builtin_bit_cast(uint64_t, tau);
+  if constexpr (sizeof(T) == 4) return make_uint2(lo32(b), hi32(b));
+  else return make_uint4(lo32(b), hi32(b), 0u, 0u);
 }
 
+__device__ __forceinline__ void log_header(char* at, uint64_t w0, uint64_t w1, uint64_t w2, uint64_t tag) {
+  uint4* h = reinterpret_cast<uint4*>(at);
+  h[0] = make_uint4(lo32(w0), hi32(w0), lo32(w1), hi32(w1));
+  h[1] = make_uint4(lo32(w2), hi32(w2), lo32(tag), hi32(tag));
+}
+
+// One trip of the wave: ev, the lane had an event; fin_with_events, its
+// particle, which had events, finished; fresh, it took a new particle at the
+// start of the trip (its launch index in L.k).
 template <typename T>
 __device__ __forceinline__ void log_trip(const StepArgs<T>& a, LogWriter& w, uint32_t wave, bool ev,
                                          bool fin_with_events, bool fresh, const Lane<T>& L) {
@@ -744,7 +750,7 @@ __device__ __forceinline__ void log_trip(const StepArgs<T>& a, LogWriter& w, uin
   constexpr uint32_t kPer = (uint32_t)log_records_per_block(S);
   const uint64_t m_part = __ballot(ev || fin_with_events);
   if (!m_part) return;
-  const uint64_t m_new = __ballot(fresh && ev), m_ev = __ballot(ev);
+  const uint64_t m_fresh = __ballot(fresh), m_ev = __ballot(ev);
   w.recs += 1;
   if (w.state == 2) return;
   const int lane = lane_id();
@@ -759,27 +765,20 @@ __device__ __forceinline__ void log_trip(const StepArgs<T>& a, LogWriter& w, uin
       return;
     }
     if (lane == 0) {
-      if (w.state == 1) {
-        char* m = a.log_pool + (uint64_t)w.blk * kLogBlock + (uint64_t)w.pos * R;
-        *reinterpret_cast<uint4*>(m) =
-            make_uint4(lo32(kLogMarkNew), hi32(kLogMarkNew), lo32(kLogMarkJump), hi32(kLogMarkJump));
-        *reinterpret_cast<uint64_t*>(m + 16) = blk;
-      } else {
-        a.log_head[wave] = blk + 1;
-      }
+      if (w.state == 1) log_header(a.log_pool + (uint64_t)w.blk * kLogBlock + (uint64_t)w.pos * R, 0, 0, blk, kLogJump);
+      else a.log_head[wave] = blk + 1;
     }
     w.state = 1;
     w.blk = b;
     w.pos = 0;
   }
+  // fresh lanes took consecutive launch indices in lane order (one queue range per trip)
+  const uint64_t base = m_fresh ? readlane64((uint64_t)L.k, __builtin_ctzll(m_fresh)) : 0ull;
   char* rec = a.log_pool + (uint64_t)w.blk * kLogBlock + (uint64_t)w.pos * R;
-  if (lane == 0) *reinterpret_cast<uint4*>(rec) = make_uint4(lo32(m_new), hi32(m_new), lo32(m_ev), hi32(m_ev));
-  if (ev || fin_with_events) {
-    const LogSlot<T> sl = ev ? log_event_slot<T>(L.lz, L.lh, L.lu, L.k) : log_final_slot<T>(L.tau);
-    uint4* d = reinterpret_cast<uint4*>(rec + 16 + (uint64_t)S * lane);
-#pragma unroll
-    for (int c = 0; c < (int)(S / 16); ++c) d[c] = sl.c[c];
-  }
+  if (lane == 0) log_header(rec, m_fresh, m_ev, base, kLogRecord);
+  if (ev || fin_with_events)
+    *reinterpret_cast<LogSlot<T>*>(rec + kLogHeader + (uint64_t)S * lane) =
+        ev ? log_event_slot<T>(L.lz, L.lh) : log_final_slot<T>(L.tau);
   w.pos += 1;
 }
 
@@ -789,9 +788,7 @@ __device__ __forceinline__ void log_close(const StepArgs<T>& a, const LogWriter&
   constexpr uint64_t kPer = log_records_per_block(log_slot_bytes<T>());
   if (lane_id() != 0) return;
   if (w.state == 0) a.log_head[wave] = 0;
-  else if (w.state == 1)
-    *reinterpret_cast<uint4*>(a.log_pool + (uint64_t)w.blk * kLogBlock + (uint64_t)w.pos * R) =
-        make_uint4(lo32(kLogMarkNew), hi32(kLogMarkNew), lo32(kLogMarkEnd), hi32(kLogMarkEnd));
+  else if (w.state == 1) log_header(a.log_pool + (uint64_t)w.blk * kLogBlock + (uint64_t)w.pos * R, 0, 0, 0, kLogEnd);
   // the blocks this wave's records take (each block keeps its last position
   // for a marker), plus one for the end marker
   if (w.recs) atomicAdd(a.log_ctl + kLogNeed, (unsigned long long)(w.recs / (kPer - 1) + 2) * kLogBlock);
@@ -821,7 +818,7 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   int32_t local_max = 0;
   bool capped = false;
   while (true) {
-    const uint64_t k = wq_take(wq, !have, n, a.queue, waves);
+    const uint64_t k = wq_take<kLog>(wq, !have, n, a.queue, waves);
     bool fresh = false;
     if (!have && k < n) {
       load_state<T, kMain>(a, lt.src, (int64_t)k, L);
@@ -1231,17 +1228,19 @@ __device__ __forceinline__ void advance_lepton_ct(Lane<T>& L, T q, T h) {
 }
 
 // One event replayed from the log: the arithmetic of lepton_iter's event
-// branch with z, h and the child's optical depth taken from the log, so the
-// child record and the particle's state come out bit for bit the same.
+// branch with z and h taken from the log (the event's draws come from the
+// same Philox counters), so the child record and the particle's state come
+// out bit for bit the same.
 template <typename T, bool kPush, bool kPos>
-__device__ __forceinline__ void replay_event(const StepArgs<T>& a, Lane<T>& L, T q, T z, T h, uint32_t u,
-                                             int64_t obase, Outbox<T>& O) {
+__device__ __forceinline__ void replay_event(const StepArgs<T>& a, Lane<T>& L, T q, T z, T h, int64_t obase,
+                                             Outbox<T>& O) {
   advance_lepton_ct<T, kPush, kPos>(L, q, h);
   L.t += h;
   T d, omd;
   sigmoid_of<T>(z, d, omd);
   const int64_t o = obase + L.j;
   if (o < a.out_cap) {  // the photon: k = delta p, born here
+    const uint32_t u = draw(a.seed, L.id, a.step, (uint32_t)L.j).z;
     const uint4 v = draw(a.seed, L.id, a.step, (uint32_t)L.j | 0x80000000u);
     O.r.px = d * L.p[0];
     O.r.py = d * L.p[1];
@@ -1302,17 +1301,17 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   const uint64_t me = 1ull << lane;
   uint64_t blk = head - 1;
   uint32_t pos = 0;
-  // a record and, fetched while the current one is handled, the next
-  auto fetch = [&](uint32_t p, uint4& hd, LogSlot<T>& sl) {
+  // a record (header words m_fresh, m_ev | base, tag, and the lane's slot)
+  // and, fetched while the current one is handled, the next
+  auto fetch = [&](uint32_t p, uint4& h0, uint4& h1, LogSlot<T>& sl) {
     const char* r = a.log_pool + blk + (uint64_t)p * R;
-    hd = *reinterpret_cast<const uint4*>(r);
-    const uint4* qs = reinterpret_cast<const uint4*>(r + 16 + (uint64_t)S * lane);
-#pragma unroll
-    for (int c = 0; c < (int)(S / 16); ++c) sl.c[c] = qs[c];
+    h0 = reinterpret_cast<const uint4*>(r)[0];
+    h1 = reinterpret_cast<const uint4*>(r)[1];
+    sl = *reinterpret_cast<const LogSlot<T>*>(r + kLogHeader + (uint64_t)S * lane);
   };
-  uint4 hd;
+  uint4 h0, h1;
   LogSlot<T> sl;
-  fetch(pos, hd, sl);
+  fetch(pos, h0, h1, sl);
   Lane<T> L;
   Outbox<T> O;
   O.what = 0;
@@ -1322,24 +1321,23 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   int64_t obase = 0;
   bool have = false;
   while (true) {
-    const uint64_t m_new = join64(hd.x, hd.y), m_ev = join64(hd.z, hd.w);
-    if (log_is_marker(m_new, m_ev)) {
-      if (m_ev == kLogMarkEnd) break;
-      blk = join64(__builtin_amdgcn_readlane((int)sl.c[0].x, 0), __builtin_amdgcn_readlane((int)sl.c[0].y, 0));
+    const uint64_t m_fresh = join64(h0.x, h0.y), m_ev = join64(h0.z, h0.w);
+    const uint64_t tag = join64(h1.z, h1.w);
+    if (tag != kLogRecord) {
+      if (tag == kLogEnd) break;
+      blk = join64(h1.x, h1.y);  // kLogJump: the block the log goes on in
       pos = 0;
-      fetch(pos, hd, sl);
+      fetch(pos, h0, h1, sl);
       continue;
     }
     // the next record (a record never sits at a block's last position)
-    uint4 hd_n;
+    uint4 h0_n, h1_n;
     LogSlot<T> sl_n;
-    fetch(pos + 1, hd_n, sl_n);
+    fetch(pos + 1, h0_n, h1_n, sl_n);
     const bool ev = (m_ev & me) != 0;
     const bool fin = have && !ev;
-    if (m_new & me) {
-      int64_t k;
-      if constexpr (sizeof(T) == 4) k = (int64_t)sl.c[0].w;
-      else k = (int64_t)join64(sl.c[1].z, sl.c[1].w);
+    if (m_fresh & m_ev & me) {  // a new particle with an event (log_fresh_index)
+      const int64_t k = (int64_t)(join64(h1.x, h1.y) + mbcnt(m_fresh));
       load_state<T, kMain, kPush>(a, src, k, L);
       if (!kMain && kPush) load_fields<T>(src, L.root, L.E, L.B);
       if constexpr (!kPos) L.x[0] = L.x[1] = L.x[2] = T(0);
@@ -1349,19 +1347,16 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
     }
     if (ev) {
       T z, h;
-      uint32_t u;
       if constexpr (sizeof(T) == 4) {
-        z = __builtin_bit_cast(float, sl.c[0].x);
-        h = __builtin_bit_cast(float, sl.c[0].y);
-        u = sl.c[0].z;
+        z = __builtin_bit_cast(float, sl.x);
+        h = __builtin_bit_cast(float, sl.y);
       } else {
-        z = __builtin_bit_cast(double, join64(sl.c[0].x, sl.c[0].y));
-        h = __builtin_bit_cast(double, join64(sl.c[0].z, sl.c[0].w));
-        u = sl.c[1].x;
+        z = __builtin_bit_cast(double, join64(sl.x, sl.y));
+        h = __builtin_bit_cast(double, join64(sl.z, sl.w));
       }
-      replay_event<T, kPush, kPos>(a, L, q, z, h, u, obase, O);
+      replay_event<T, kPush, kPos>(a, L, q, z, h, obase, O);
     } else if (fin) {
-      const double tf = __builtin_bit_cast(double, join64(sl.c[0].x, sl.c[0].y));
+      const double tf = __builtin_bit_cast(double, join64(sl.x, sl.y));
       if (L.t < dtT) {  // no event before the end of the step (the count pass's last trip)
         advance_lepton_ct<T, kPush, kPos>(L, q, dtT - L.t);
         L.t = dtT;
@@ -1385,7 +1380,8 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
     flush<T>(a, src, O);
     if constexpr (kStage) line_flush<kReplayLine, T>(wave_slots, owners[threadIdx.x >> 6], cl, fin);
     if (fin) have = false;
-    hd = hd_n;
+    h0 = h0_n;
+    h1 = h1_n;
     sl = sl_n;
     pos += 1;
   }

@@ -1,13 +1,14 @@
 """Host model of the lepton count pass's event log and its replay (CPU).
 
 ``event_log_model.cpp`` writes the log of one wave over random particles
-with the count kernel's lane discipline and the format of csrc/event_log.h,
-reads it back as the replay kernel does, and requires every particle with
-events to get its launch index, its events in order and its final optical
-depth back, across block jumps and trips on which every lane takes a new
-particle.  It must also find the earlier reader wrong, which took every
-header with all 64 lanes new for a marker (on the GPU that read an entry's
-bits as a block offset and faulted).
+with the count kernel's lane discipline (a queue of shuffled chunks, one
+chunk per trip) and the format of csrc/event_log.h, reads it back as the
+replay kernel does, and requires every particle with events to get its launch
+index, its events in order and its final optical depth back, across block
+jumps, trips on which every lane takes a new particle, and fresh lanes whose
+particle has no event.  It must also find two variants wrong: a reader that
+ranks a new lane among the fresh lanes with an event only, and a writer whose
+queue serves a trip from two chunks.
 """
 import subprocess
 from pathlib import Path
