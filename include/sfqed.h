@@ -27,9 +27,19 @@
  * therefore not overlap on the GPU: issue them on one stream, or synchronise
  * before switching streams.
  *
+ * Library scratch: qed_step and qed_step_merged keep per-device scratch in
+ * library-owned device memory that grows (hipMalloc) to the largest launch
+ * so far: per-particle counts and offsets, and the event log of the lepton
+ * count pass, which the write pass replays.  After a step the log grows to
+ * 5/4 of what the step needed, as long as that is at most half of the free
+ * device memory; launches whose log does not fit are written by re-running
+ * their event loop instead (the same results).  The scratch lives until the
+ * process ends.
+ *
  * Environment: SFQED_WRITE_STAGING=0 makes the FP32 step store each child
- * record directly instead of staging it in LDS (the same records, slower); it
- * exists so that the two paths can be compared.
+ * record directly instead of staging it in LDS; SFQED_WRITE_REPLAY=0 turns
+ * the event log off (the write pass re-runs every event loop).  Both give the
+ * same results, slower; they exist so that the paths can be compared.
  *
  * Errors: every function returns a qed_status and never aborts.  Invalid
  * arguments are rejected before any work is queued.
