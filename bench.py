@@ -284,8 +284,9 @@ def cascade_bench(sf, torch, steps: int, n_seeds: int, merged: bool = True) -> d
 def cascade_leg(sf, torch, n_seeds: int = 1_000_000, steps: int = 20) -> dict:
     """The rotating-field cascade as an extra leg of the default run: push on,
     merge every step, n_seeds electrons growing ~200x.  One untimed run sizes
-    the library's scratch, the second is reported: host time per step, and
-    the dominant kernel (HIP events in the library, on the step's stream) with
+    the library's scratch, the second is timed (host time per step), and a
+    third with HIP events around every kernel (on the step's stream; the events
+    add launch gaps, so the timed run has none) gives the dominant kernel with
     its algorithmic bytes against 8 TB/s."""
     import synth
     from paper_2409_17299_amd import cascade
@@ -295,14 +296,17 @@ def cascade_leg(sf, torch, n_seeds: int = 1_000_000, steps: int = 20) -> dict:
     sp = [(s.p, s.w, s.tau, s.id) for s in wl.species]
     cap = [n_seeds * 80, n_seeds * 80, n_seeds * 300]
     app = [n_seeds * 20, n_seeds * 20, n_seeds * 80]
-    cfg = sf.step_cfg(push=True, nev=False, profile=True)
-    for rep in range(2):
+    runs = []
+    for profile in (False, False, True):
+        cfg = sf.step_cfg(push=True, nev=False, profile=profile)
         counts, stats, secs, main, _ = cascade.run(tables, sp, wl.dt, steps,
                                                    lambda k: synth.rotating_field(e0, wdt, k), cap, app,
                                                    dtype=torch.float32, seed=0, cfg=cfg)
+        runs.append((counts, stats, secs))
         del main
         torch.cuda.empty_cache()
-    S = sum_stats(stats)
+    counts, _, secs = runs[1]
+    S = sum_stats(runs[2][1])
     n_main = [int(v) for v in counts[:-1].sum(axis=0)]  # input particles over all steps
     kern = {}
     for k, name in enumerate(sf.StepStats.KERNELS):
@@ -600,6 +604,9 @@ def main(argv=None):
     tables = sf.Tables()
     dtype = torch.float32
     cfg = sf.step_cfg(push=False, gamma_min=args.gamma_min, profile=True, nev=False)
+    # the timed steps run without HIP events around the kernels (they add launch
+    # gaps); the same steps are then run again with them for the per-kernel times
+    cfg_timed = sf.step_cfg(push=False, gamma_min=args.gamma_min, profile=False, nev=False)
 
     # size the append buffers with one generous step
     caps = [int(args.n * 12), int(args.n * 12), int(min(args.n * 100, (1 << 30) - 1024))]
@@ -629,13 +636,22 @@ def main(argv=None):
     stats = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        rc, st = dw.step(tables, args.warmup + i, cfg, merged=not args.two_call)
+        rc, st = dw.step(tables, args.warmup + i, cfg_timed, merged=not args.two_call)
         assert rc == 0, rc
         stats.append(st)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = el * 1e3 / args.steps
     S = sum_stats(stats)
+    profiled = []
+    for i in range(args.steps):  # the same steps (same work) with the kernels timed
+        rc, st = dw.step(tables, args.warmup + i, cfg, merged=not args.two_call)
+        assert rc == 0, rc
+        profiled.append(st)
+    P = sum_stats(profiled)
+    assert P["n_emit"] == S["n_emit"] and P["n_pair"] == S["n_pair"]
+    for key in ("kernel_ms", "kernel_launches", "kernel_particles"):
+        S[key] = P[key]
     log(f"timed: {args.steps} steps in {el:.3f} s ({ms:.2f} ms/step); per-kernel ms "
         f"{dict(zip(sf.StepStats.KERNELS, [round(v / args.steps, 3) for v in S['kernel_ms']]))}; "
         f"lepton launches written from the event log {S['log_replays']}, by the direct write kernel "

@@ -66,6 +66,9 @@ struct Scratch {
   uint64_t log_cap = 0;
   uint64_t* log_head = nullptr;
   int64_t log_waves = 0;
+  // pinned host words for the step's small read-backs (a copy into pageable
+  // memory goes through a staging buffer: two copies instead of one)
+  int64_t* pin = nullptr;
   std::mutex mu;
 };
 
@@ -92,6 +95,10 @@ Scratch* scratch_for_current_device() {
   if (hipMemset(s->ctrl, 0, sizeof(uint64_t) * kCtrlWords) != hipSuccess) {
     delete s;
     return nullptr;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->pin), 64, hipHostMallocDefault) != hipSuccess) {
+    s->pin = nullptr;  // read-backs then go to pageable memory
+    (void)hipGetLastError();
   }
   g_scratch.push_back(s);
   return s;
@@ -570,8 +577,9 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   std::memset(&local, 0, sizeof(local));
   int64_t cur[2] = {0, 0};  // photons, leptons appended so far
   auto read_cursors = [&]() -> qed_status {
-    int64_t h[2];
-    SFQED_HIP(hipMemcpyAsync(h, S->ctrl + kCurPhoton, sizeof(h), hipMemcpyDeviceToHost, st));
+    int64_t local_h[2];
+    int64_t* h = S->pin ? S->pin : local_h;
+    SFQED_HIP(hipMemcpyAsync(h, S->ctrl + kCurPhoton, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SFQED_HIP(hipStreamSynchronize(st));
     cur[0] = h[0];
     cur[1] = h[1];
