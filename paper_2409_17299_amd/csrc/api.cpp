@@ -35,6 +35,7 @@ constexpr int kStats = kSlots + 8;      // 8 words
 constexpr int kResampleCount = kSlots + 16;  // 3 words: survivors of each species' compaction
 constexpr int kMergedCursor = kSlots + 24;   // photons in the main arrays so far (qed_step_merged)
 constexpr int kNonFinite = kSlots + 32;      // 3 words: particles with non-finite values (qed_validate)
+constexpr size_t kPinBytes = 256;            // pinned host bytes for read-backs
 
 // Library-owned scratch of one device: per-particle counts, offsets and event
 // list of the largest launch so far, look-back words, and a control block.
@@ -66,8 +67,8 @@ struct Scratch {
   uint64_t log_cap = 0;
   uint64_t* log_head = nullptr;
   int64_t log_waves = 0;
-  // pinned host words for the step's small read-backs (a copy into pageable
-  // memory goes through a staging buffer: two copies instead of one)
+  // pinned host words for small read-backs (a copy into pageable memory goes
+  // through a staging buffer: two copies instead of one)
   int64_t* pin = nullptr;
   std::mutex mu;
 };
@@ -96,12 +97,22 @@ Scratch* scratch_for_current_device() {
     delete s;
     return nullptr;
   }
-  if (hipHostMalloc(reinterpret_cast<void**>(&s->pin), 64, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->pin), kPinBytes, hipHostMallocDefault) != hipSuccess) {
     s->pin = nullptr;  // read-backs then go to pageable memory
     (void)hipGetLastError();
   }
   g_scratch.push_back(s);
   return s;
+}
+
+// Copies `bytes` from the device to dst once `st` has run up to here, through
+// the pinned words when they exist and the copy fits.
+qed_status read_back(Scratch* S, void* dst, const void* src, size_t bytes, hipStream_t st) {
+  void* h = (S->pin && bytes <= kPinBytes) ? static_cast<void*>(S->pin) : dst;
+  SFQED_HIP(hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, st));
+  SFQED_HIP(hipStreamSynchronize(st));
+  if (h != dst) std::memcpy(dst, h, bytes);
+  return QED_OK;
 }
 
 qed_status ensure_scratch(Scratch* s, int64_t n) {
@@ -544,8 +555,8 @@ qed_status validate_impl(Scratch* S, const qed_ensemble* ens, int64_t bad[3], hi
     SFQED_HIP(launch_count_nonfinite<T>(view_of<T>(ens->s[s]), fields_of<T>(ens->f[s], n), n, cnt + s, st));
   }
   uint64_t h[3];
-  SFQED_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
-  SFQED_HIP(hipStreamSynchronize(st));
+  const qed_status rb = read_back(S, h, cnt, sizeof(h), st);
+  if (rb != QED_OK) return rb;
   for (int s = 0; s < 3; ++s) bad[s] = (int64_t)h[s];
   if (h[0] || h[1] || h[2]) {
     set_error("non-finite values in " + std::to_string(h[0]) + " electrons, " + std::to_string(h[1]) +
@@ -576,15 +587,7 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   qed_step_stats local;
   std::memset(&local, 0, sizeof(local));
   int64_t cur[2] = {0, 0};  // photons, leptons appended so far
-  auto read_cursors = [&]() -> qed_status {
-    int64_t local_h[2];
-    int64_t* h = S->pin ? S->pin : local_h;
-    SFQED_HIP(hipMemcpyAsync(h, S->ctrl + kCurPhoton, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    SFQED_HIP(hipStreamSynchronize(st));
-    cur[0] = h[0];
-    cur[1] = h[1];
-    return QED_OK;
-  };
+  auto read_cursors = [&]() -> qed_status { return read_back(S, cur, S->ctrl + kCurPhoton, sizeof(cur), st); };
   const int64_t capg = app[2].capacity, capl = std::min(app[0].capacity, app[1].capacity);
   EventLog log;
   log.on = cfg->profile != 0;
@@ -659,8 +662,7 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
     ++rounds;
   }
   uint64_t dev_stats[8];
-  SFQED_HIP(hipMemcpyAsync(dev_stats, S->ctrl + kStats, sizeof(dev_stats), hipMemcpyDeviceToHost, st));
-  SFQED_HIP(hipStreamSynchronize(st));
+  if ((rc = read_back(S, dev_stats, S->ctrl + kStats, sizeof(dev_stats), st)) != QED_OK) return rc;
   grow_log(S, dev_stats[kStatLogNeed]);  // later steps replay launches this one had to re-run
   local.n_emit = cur[0];
   local.n_pair = cur[1];
@@ -689,8 +691,7 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
   if (merged) {
     // the photons are merged; the leptons' records go after the input leptons
     int64_t photons = 0;
-    SFQED_HIP(hipMemcpyAsync(&photons, S->ctrl + kMergedCursor, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    SFQED_HIP(hipStreamSynchronize(st));
+    if ((rc = read_back(S, &photons, S->ctrl + kMergedCursor, sizeof(int64_t), st)) != QED_OK) return rc;
     if (ens->s[0].count + app[0].count > ens->s[0].capacity || ens->s[1].count + app[1].count > ens->s[1].capacity ||
         photons > ens->s[2].capacity) {
       ens->s[2].count = std::min(photons, ens->s[2].capacity);
@@ -864,16 +865,15 @@ qed_status resample_impl(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_res
                                      S->level + k * part_words, dstate + k, st));
   }
   LevelState ls[3];
-  SFQED_HIP(hipMemcpyAsync(ls, dstate, sizeof(ls), hipMemcpyDeviceToHost, st));
-  SFQED_HIP(hipStreamSynchronize(st));
+  qed_status rb = read_back(S, ls, dstate, sizeof(ls), st);
+  if (rb != QED_OK) return rb;
   for (int k = 0; k < 3; ++k) {
     if (!solve[k]) continue;
     const SpeciesView<T> v = view_of<T>(ens->s[k]);
     while (!ls[k].done && ls[k].iterations < 100) {
       SFQED_HIP(launch_level_pass<T>(v, ens->s[k].count, k == 2 ? 1 : 0, e_min2, cfg->target[k], 0,
                                      S->level + k * part_words, dstate + k, st));
-      SFQED_HIP(hipMemcpyAsync(&ls[k], dstate + k, sizeof(LevelState), hipMemcpyDeviceToHost, st));
-      SFQED_HIP(hipStreamSynchronize(st));
+      if ((rb = read_back(S, &ls[k], dstate + k, sizeof(LevelState), st)) != QED_OK) return rb;
     }
     if (cfg->target[k] > 0) S->level_passes[k] = std::max(2, std::min(kLevelDevicePasses, ls[k].iterations + 1));
   }
@@ -926,8 +926,7 @@ qed_status resample_impl(qed_ensemble* ens, const qed_resample_cfg* cfg, qed_res
   }
   if (compacted[0] || compacted[1] || compacted[2]) {
     int64_t kept[3] = {0, 0, 0};
-    SFQED_HIP(hipMemcpyAsync(kept, S->ctrl + kResampleCount, sizeof(kept), hipMemcpyDeviceToHost, st));
-    SFQED_HIP(hipStreamSynchronize(st));
+    if ((rb = read_back(S, kept, S->ctrl + kResampleCount, sizeof(kept), st)) != QED_OK) return rb;
     for (int k = 0; k < 3; ++k)
       if (compacted[k]) ens->s[k].count = stats.count_after[k] = kept[k];
   }
