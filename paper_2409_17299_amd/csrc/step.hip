@@ -20,7 +20,9 @@
 // The append order therefore is: particles in index order, children of one
 // particle in event order -- the same for every run and every grid size.
 
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 
 #include "lib.h"
 #include "line_rule.h"
@@ -1831,10 +1833,17 @@ __global__ void k_append_records(SpeciesView<T> d, int64_t at, const Rec<T>* rec
 // ------------------------------------------------------------------ explicit instantiations via launchers
 template <typename K, typename A>
 hipError_t launch_step_kernel(K kernel, const A& a, int grid, size_t lds, hipStream_t st, int threads = kStepThreads) {
-  if (lds > 65536) {
-    const hipError_t e =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  if (lds > 65536) {  // raise the kernel's dynamic LDS limit once per size (a host call per launch otherwise)
+    static std::mutex mu;
+    static std::unordered_map<const void*, size_t> set;  // per kernel: the largest limit set so far
+    const void* f = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lk(mu);
+    size_t& have = set[f];
+    if (lds > have) {
+      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      have = lds;
+    }
   }
   hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, st, a);
   return hipGetLastError();
