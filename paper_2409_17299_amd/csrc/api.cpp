@@ -372,11 +372,16 @@ template <typename T>
 qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const qed_step_cfg* cfg,
                       const qed_ensemble* ens, qed_append* app, int species, bool from_main, int64_t begin0,
                       int64_t n0, int64_t begin1, int64_t n1, double dt, uint64_t seed, uint32_t step, int* slot,
-                      bool positions, EventLog& log, qed_step_stats* stats, bool merged = false) {
-  // part 0: species, particles [begin0, begin0 + n0); part 1 (leptons): species + 1, [begin1, begin1 + n1)
+                      bool positions, EventLog& log, qed_step_stats* stats, bool merged = false,
+                      bool device_n = false) {
+  // part 0: species, particles [begin0, begin0 + n0); part 1 (leptons): species + 1, [begin1, begin1 + n1).
+  // device_n (appended photons of a merged step): n0 is only a bound, the
+  // range ends where the photon cursor stands when the launch runs; its events
+  // are listed up to the lepton capacity (more pairs overflow anyway)
   const int64_t n = n0 + n1;
   if (n <= 0) return QED_OK;
-  qed_status rc = ensure_scratch(S, n);
+  const int64_t list_bound = std::min(app[0].capacity, app[1].capacity);
+  qed_status rc = ensure_scratch(S, device_n ? std::max<int64_t>(std::min(n, list_bound), 1) : n);
   if (rc != QED_OK) return rc;
   if (*slot + kLaunchWords > kSlots) {
     SFQED_HIP(hipMemsetAsync(S->ctrl, 0, sizeof(uint64_t) * kSlots, st));
@@ -398,8 +403,12 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   a.begin[1] = begin1;
   a.species = species;
   a.from_main = from_main ? 1 : 0;
-  a.n0 = n0;
+  a.n0 = device_n ? INT64_MAX : n0;
   a.n = n;
+  a.n_dev = device_n ? reinterpret_cast<const int64_t*>(S->ctrl + kCurPhoton) : nullptr;
+  a.n_base = begin0;
+  a.n_cap = app[2].capacity;
+  a.list_cap = S->cap;
   for (int k = 0; k < 3; ++k) a.f[k] = fields_of<T>(ens->f[k], ens->s[k].count);
   int64_t* cursor;
   if (photon) {
@@ -538,7 +547,7 @@ qed_status run_launch(Scratch* S, hipStream_t st, const qed_tables* tab, const q
   for (int k : {k_count, 1, k_write}) {
     if (k == 1 && fold) continue;
     stats->kernel_launches[k] += 1;
-    stats->kernel_particles[k] += n;
+    stats->kernel_particles[k] += device_n ? 0 : n;  // a device-sized range is added after the round
   }
   return QED_OK;
 }
@@ -603,11 +612,33 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
     return run_launch<T>(S, st, tab, cfg, ens, app, species, from_main, begin0, n0, begin1, n1, dt, seed, step,
                          &slot, positions, log, &local, merged);
   };
+  // The photons appended from g_from on, as far as the round's lepton launch
+  // got.  qed_step has read the photon cursor back (cur[0]); the merged
+  // step's photon pass reads it on the device (one host wait less per round).
+  auto launch_appended_photons = [&](int64_t g_from) -> qed_status {
+    if (!merged) return launch(2, false, g_from, cur[0] - g_from, 0, 0);
+    if (capg - g_from <= 0) return QED_OK;
+    ++launches;
+    return run_launch<T>(S, st, tab, cfg, ens, app, 2, false, g_from, capg - g_from, 0, 0, dt, seed, step, &slot,
+                         positions, log, &local, true, true);
+  };
+  // after the round's read-back: the appended photons the round processed
+  auto photons_done = [&](int64_t g_from) -> int64_t {
+    const int64_t g_hi = std::min(cur[0], capg);
+    if (merged && g_hi > g_from) {  // a device-sized range: its particles are known only now
+      local.kernel_particles[3] += g_hi - g_from;
+      local.kernel_particles[4] += g_hi - g_from;
+    }
+    return g_hi;
+  };
   // round 0: the input ensemble, then the photons its leptons emitted
   if ((rc = launch(0, true, 0, ens->s[0].count, 0, ens->s[1].count)) != QED_OK) return rc;
-  if ((rc = read_cursors()) != QED_OK) return rc;
   int64_t g_done = 0;
-  bool overflow = cur[0] > capg;
+  bool overflow = false;
+  if (!merged) {
+    if ((rc = read_cursors()) != QED_OK) return rc;
+    overflow = cur[0] > capg;
+  }
   if (!overflow) {
     if ((rc = launch(2, true, 0, ens->s[2].count, 0, 0)) != QED_OK) return rc;
     // merged: the input photons are read for the last time in this round, so
@@ -638,10 +669,9 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
       slot += kLaunchWords;
       SFQED_HIP(launch_merge_photons<T>(m, st));
     }
-    const int64_t g_hi = cur[0];
-    if ((rc = launch(2, false, 0, g_hi, 0, 0)) != QED_OK) return rc;
-    g_done = g_hi;
+    if ((rc = launch_appended_photons(0)) != QED_OK) return rc;
     if ((rc = read_cursors()) != QED_OK) return rc;
+    g_done = photons_done(0);
     overflow = cur[0] > capg || cur[1] > capl;
   }
   int64_t rounds = 1, l_done = 0;
@@ -649,15 +679,16 @@ qed_status step_impl(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensembl
     const int64_t l_hi = cur[1];
     if ((rc = launch(0, false, l_done, l_hi - l_done, l_done, l_hi - l_done)) != QED_OK) return rc;
     l_done = l_hi;
-    if ((rc = read_cursors()) != QED_OK) return rc;
-    if (cur[0] > capg) {
-      overflow = true;
-      break;
+    if (!merged) {
+      if ((rc = read_cursors()) != QED_OK) return rc;
+      if (cur[0] > capg) {
+        overflow = true;
+        break;
+      }
     }
-    const int64_t g_hi = cur[0];
-    if ((rc = launch(2, false, g_done, g_hi - g_done, 0, 0)) != QED_OK) return rc;
-    g_done = g_hi;
+    if ((rc = launch_appended_photons(g_done)) != QED_OK) return rc;
     if ((rc = read_cursors()) != QED_OK) return rc;
+    g_done = photons_done(g_done);
     overflow = cur[0] > capg || cur[1] > capl;
     ++rounds;
   }

@@ -116,10 +116,16 @@ struct StepArgs {
   SpeciesView<T> dst;               // the main photons
   int64_t dst_cap;                  // their capacity (nothing is written at or past it)
   int64_t* dst_cursor;              // photons in dst so far: read by the first tile, set by the last
-  uint64_t* dst_state;              // look-back words, one per tile of kStepThreads photons
+  uint64_t* dst_state;              // look-back words, one per tile of kMergedTile photons
   uint32_t dst_epoch;
   unsigned long long* dst_ticket;   // tile counter, zero at launch
   int64_t* pair_cursor;             // pairs appended so far (the scan's cursor of a photon launch)
+  // a merged range sized on the device: photons [n_base, min(*n_dev, n_cap)) of
+  // the append buffer (the photon cursor after the round's lepton launch), so
+  // that the host need not read the cursor back first; null: n photons
+  const int64_t* n_dev;
+  int64_t n_base, n_cap;
+  int64_t list_cap;                 // entries of list and offsets (events past it are not listed)
   // lepton launches: the count pass's event log, replayed by the write pass
   char* log_pool;                   // log blocks
   uint64_t log_cap;                 // bytes of log_pool (0: the count pass only measures the log)

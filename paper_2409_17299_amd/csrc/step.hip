@@ -898,7 +898,12 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
   const LdsTables lt = stage_tables<T, true>(a, lds);
   __shared__ int32_t wsum[kMergedItems][kStepThreads / 64];
   __shared__ int64_t s_tile, s_base;
-  const int64_t num_tiles = (a.n + kMergedTile - 1) / kMergedTile;
+  int64_t n = a.n;
+  if (a.n_dev) {  // the range as the round's lepton launch left it
+    const int64_t hi = *a.n_dev < a.n_cap ? *a.n_dev : a.n_cap;
+    n = hi > a.n_base ? hi - a.n_base : 0;
+  }
+  const int64_t num_tiles = (n + kMergedTile - 1) / kMergedTile;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t dst0 = *a.dst_cursor, pair0 = *a.pair_cursor;
   int32_t any_event = 0;
@@ -916,7 +921,7 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
 #pragma unroll
     for (int it = 0; it < kMergedItems; ++it) {
       const int64_t k = tile * kMergedTile + (int64_t)it * kStepThreads + threadIdx.x;
-      if (k < a.n) {
+      if (k < n) {
         Lane<T> L;
         load_lane<T>(a, lt.src, k, L);
         photon_iter<T, false>(a, lt, L, 0);
@@ -958,10 +963,13 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
       if (lane == 0) {
         s_base = b;
         if (tile == num_tiles - 1) {
-          const int64_t events = a.n - (b + total);
+          const int64_t events = n - (b + total);
           *a.dst_cursor = dst0 + b + total;
           *a.pair_cursor = pair0 + events;
-          *const_cast<int64_t*>(a.list_len) = events;  // a control word the scan writes in other launches
+          // a control word the scan writes in other launches; events past the
+          // list's capacity make pairs past the lepton capacity, an overflow
+          // the host reports, and are not written
+          *const_cast<int64_t*>(a.list_len) = events < a.list_cap ? events : a.list_cap;
           atomicAdd(&a.stats[kStatEventParticles + 1], (unsigned long long)events);
         }
       }
@@ -973,8 +981,10 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
       if ((event >> it) & 1u) {  // the e-th event of the launch, e = k - survivors before k
         const int64_t k = tile * kMergedTile + (int64_t)it * kStepThreads + threadIdx.x;
         const int64_t e = k - (s_base + pre[it]);
-        a.list[e] = (int32_t)k;
-        a.offsets[e] = pair0 + e;
+        if (e < a.list_cap) {
+          a.list[e] = (int32_t)k;
+          a.offsets[e] = pair0 + e;
+        }
       }
       if (!((surv >> it) & 1u)) continue;
       const int64_t o = dst0 + s_base + pre[it];

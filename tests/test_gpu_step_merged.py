@@ -89,6 +89,26 @@ def test_photon_capacity():
     assert main[2].count <= main[2].capacity
 
 
+def test_append_capacity():
+    """The merged step sizes each round's appended-photon range on the device,
+    clamped to the append capacity: with a photon append buffer far too small
+    it reports the overflow with the capacity it would have needed and writes
+    nothing past any capacity."""
+    torch, sf = need_gpu()
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 2000), np.arange(0, 4_000_000, 2000),
+                                                  np.arange(0, 2_000_000, 2000)])
+    main, fields, app = build(sf, torch, wl, torch.float32, app_cap=(400_000, 400_000, 10_000))
+    app[2].cap = 5_000  # the library sees 5,000 records; the 5,000 behind them must stay untouched
+    rc, st = sf.step_merged(sf.Tables(), main, fields, app, wl.dt, 0, 0, sf.step_cfg(push=False, gamma_min=2.0),
+                            check=False)
+    torch.cuda.synchronize()
+    assert rc == 2
+    assert st.required_capacity[2] > 5_000
+    assert app[2].count <= 5_000 and main[2].count <= main[2].capacity
+    rec = app[2].rec_dtype.itemsize
+    assert not app[2].data[5_000 * rec:].any()
+
+
 def test_staged_records_equal_direct_stores(monkeypatch):
     """The FP32 lepton write kernel stages child records in LDS and writes them
     in half lines; with SFQED_WRITE_STAGING=0 it stores each record directly
