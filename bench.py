@@ -355,29 +355,51 @@ def per_particle_leg(sf, torch, n_chunk: int = 20_000_000, passes: int = 10) -> 
         parts.append((s, proc, st, f, k))
     del wl
 
+    chis = [None, None]
+
+    def evals():
+        for j, (s, proc, st, f, k) in enumerate(parts):
+            chis[j], _ = sf.eval_particles(tables, s, st, f)
+
+    def samples():
+        for j, (s, proc, st, f, k) in enumerate(parts):
+            sf.sample(tables, proc, chis[j], k)
+
     def one_pass():
-        for s, proc, st, f, k in parts:
-            chi, _ = sf.eval_particles(tables, s, st, f)
-            sf.sample(tables, proc, chi, k)
+        evals()
+        samples()
+
+    def timed(fn) -> float:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(passes):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
 
     one_pass()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(passes):
-        one_pass()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    ms = timed(one_pass)
+    # each kernel alone over the same passes (the eval outputs of the last
+    # pass feed the samples)
+    ms_eval, ms_sample = timed(evals), timed(samples)
     n_eval = n_chunk * passes
     gbs = 56.0 * n_eval / (ms * 1e-3) / 1e9
-    log(f"per-particle kernels: {n_eval:.2e} evaluations in {ms:.1f} ms, {gbs:.0f} GB/s")
+    gbs_eval = 44.0 * n_eval / (ms_eval * 1e-3) / 1e9
+    gbs_sample = 12.0 * n_eval / (ms_sample * 1e-3) / 1e9
+    log(f"per-particle kernels: {n_eval:.2e} evaluations in {ms:.1f} ms, {gbs:.0f} GB/s "
+        f"(eval alone {ms_eval:.2f} ms, {gbs_eval:.0f} GB/s; sample alone {ms_sample:.2f} ms, {gbs_sample:.0f} GB/s)")
     return {"workload": "static_b_sweep", "chi_range": [1e-3, 1e3], "dtype": "f32",
-            "kernels": "k_eval_particles + k_sample", "particles_per_pass": n_chunk, "passes": passes,
+            "kernels": "k_eval_particles + k_sample4", "particles_per_pass": n_chunk, "passes": passes,
             "evaluations": n_eval, "ms": round(ms, 3), "particles_per_s": round(n_eval / (ms * 1e-3), 1),
             "bytes_per_particle": 56,
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)},
+            "eval": {"kernel": "k_eval_particles", "ms": round(ms_eval, 3), "bytes_per_particle": 44, "bound": "hbm",
+                     "achieved_gbs": round(gbs_eval, 1), "frac": round(gbs_eval / HBM_PEAK_GBS, 4)},
+            "sample": {"kernel": "k_sample4", "ms": round(ms_sample, 3), "bytes_per_particle": 12, "bound": "alu",
+                       "samples_per_s": round(n_eval / (ms_sample * 1e-3), 1), "achieved_gbs": round(gbs_sample, 1)}}
 
 
 # ----------------------------------------------------------------------------- standing-wave test problem
@@ -563,6 +585,8 @@ def main(argv=None):
     ap.add_argument("--sw-target", type=int, default=1_000_000, help="leveling target per lepton species")
     ap.add_argument("--seeds", type=int, default=1_000_000, help="seed electrons of the rotating_e cascade")
     ap.add_argument("--gamma-min", type=float, default=2.0)
+    ap.add_argument("--per-particle", action="store_true",
+                    help="only run the per-particle kernels of the precision sweep (chi, rate, one sample)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM counters)")
     args = ap.parse_args(argv)
@@ -588,6 +612,9 @@ def main(argv=None):
         return 0
     if args.workload == "static_b_sweep":
         print(json.dumps(precision_sweep(sf, torch, 200_000_000, 10_000_000)), flush=True)
+        return 0
+    if args.per_particle:
+        print(json.dumps(per_particle_leg(sf, torch)), flush=True)
         return 0
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

@@ -123,6 +123,34 @@ def test_sampler_fp32_vs_oracle(env, orc):
     assert e1.max() < 5e-5 and np.median(e1) < 2e-6
 
 
+def test_sampler_fp32_vector_and_scalar_paths_agree(env, orc):
+    """FP32 columns that are 16-byte aligned are sampled four per thread with
+    16-byte accesses, others one per thread: both evaluate the same
+    arithmetic, so the results are equal bit for bit, also in a ragged last
+    group, and agree with the oracle."""
+    torch, sf, tabs = env
+    rng = np.random.default_rng(5)
+    for n in (1, 3, 4, 5, 1027, 4099):
+        chi = _lu(rng, 1e-4, 1e4, n).astype(np.float32)
+        k = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        for proc in (0, 1):
+            c = chi if proc == 0 else np.maximum(chi, np.float32(1e-2))
+            ca = torch.tensor(c, device="cuda")
+            ka = torch.tensor(k.view(np.int32), device="cuda")
+            # the same values one element into a larger buffer: 4-byte aligned only
+            cb = torch.zeros(n + 1, dtype=torch.float32, device="cuda")[1:]
+            kb = torch.zeros(n + 1, dtype=torch.int32, device="cuda")[1:]
+            cb.copy_(ca)
+            kb.copy_(ka)
+            assert cb.data_ptr() % 16 and ca.data_ptr() % 16 == 0
+            va = sf.sample(tabs, proc, ca, ka).cpu().numpy()
+            vb = sf.sample(tabs, proc, cb, kb).cpu().numpy()
+            assert np.array_equal(va.view(np.uint32), vb.view(np.uint32)), (n, proc)
+            ref, _ = (orc.sample_rad if proc == 0 else orc.sample_pair)(c.astype(np.float64), k)
+            rel = np.abs(va - ref) / np.maximum(ref, 1e-300)
+            assert rel.max() < 5e-5, (n, proc, rel.max())
+
+
 def test_cdf_table_nodes_vs_oracle(env, orc):
     """FP64 grid nodes: the GPU's inversion equals the oracle's at the same (chi, r)."""
     torch, sf, tabs = env
