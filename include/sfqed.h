@@ -175,10 +175,14 @@ typedef struct {
 } qed_append;
 
 /* Per-particle fields of one species (dtype of the step), indexed like the
- * particles when stride = 1, or one shared value when stride = 0. */
+ * particles when stride = 1, or one shared value when stride = 0.  n: entries
+ * per array; with stride = 1 it must be at least the species' count (the
+ * entry points that take fields return QED_ERR_ARG otherwise, before any
+ * device work); ignored with stride = 0. */
 typedef struct {
   const void *ex, *ey, *ez, *bx, *by, *bz;
   int64_t stride;
+  int64_t n;
 } qed_fields;
 
 typedef struct {

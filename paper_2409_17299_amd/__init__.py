@@ -59,7 +59,7 @@ def record_dtype(float_dtype) -> np.dtype:
 
 class CFields(C.Structure):
     _fields_ = [("ex", C.c_void_p), ("ey", C.c_void_p), ("ez", C.c_void_p), ("bx", C.c_void_p),
-                ("by", C.c_void_p), ("bz", C.c_void_p), ("stride", C.c_int64)]
+                ("by", C.c_void_p), ("bz", C.c_void_p), ("stride", C.c_int64), ("n", C.c_int64)]
 
 
 class CEnsemble(C.Structure):
@@ -406,7 +406,8 @@ class Fields:
         return cls(*[t[:, k].contiguous() for k in range(6)], stride=0 if f.shape[0] == 1 else 1)
 
     def c(self) -> CFields:
-        return CFields(*[_ptr(t) for t in (self.ex, self.ey, self.ez, self.bx, self.by, self.bz)], self.stride)
+        ts = (self.ex, self.ey, self.ez, self.bx, self.by, self.bz)
+        return CFields(*[_ptr(t) for t in ts], self.stride, min(t.numel() for t in ts))
 
 
 def _dtype_code(t) -> int:

@@ -314,10 +314,15 @@ bool append_ok(const qed_append& a, bool positions) {
   return true;
 }
 
+// n particles read these fields: with stride 1 every array must hold n entries
 bool fields_ok(const qed_fields& f, int64_t n) {
   if (n == 0) return true;
   if (!f.ex || !f.ey || !f.ez || !f.bx || !f.by || !f.bz) return false;
-  return f.stride == 0 || f.stride == 1;
+  return f.stride == 0 || (f.stride == 1 && f.n >= n);
+}
+std::string fields_error(int s) {
+  return "fields of species " + std::to_string(s) +
+         ": a missing array, a stride other than 0 or 1, or fewer entries than particles";
 }
 
 // HIP events around kernels, read once the step has finished (no extra waits).
@@ -1110,9 +1115,12 @@ qed_status qed_step(const qed_tables* tab, const qed_step_cfg* cfg, qed_ensemble
   }
   const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
   for (int s = 0; s < 3; ++s) {
-    if (!species_ok(ens->s[s], s == 2, positions) || !append_ok(app[s], positions) ||
-        !fields_ok(ens->f[s], ens->s[s].count)) {
+    if (!species_ok(ens->s[s], s == 2, positions) || !append_ok(app[s], positions)) {
       set_error("invalid species " + std::to_string(s));
+      return QED_ERR_ARG;
+    }
+    if (!fields_ok(ens->f[s], ens->s[s].count)) {
+      set_error(fields_error(s));
       return QED_ERR_ARG;
     }
   }
@@ -1134,9 +1142,12 @@ qed_status qed_step_merged(const qed_tables* tab, const qed_step_cfg* cfg, qed_e
   }
   const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
   for (int s = 0; s < 3; ++s) {
-    if (!species_ok(ens->s[s], s == 2, positions) || !append_ok(app[s], positions) ||
-        !fields_ok(ens->f[s], ens->s[s].count)) {
+    if (!species_ok(ens->s[s], s == 2, positions) || !append_ok(app[s], positions)) {
       set_error("invalid species " + std::to_string(s));
+      return QED_ERR_ARG;
+    }
+    if (!fields_ok(ens->f[s], ens->s[s].count)) {
+      set_error(fields_error(s));
       return QED_ERR_ARG;
     }
   }
@@ -1152,8 +1163,12 @@ qed_status qed_validate(const qed_ensemble* ens, int64_t bad[3], void* stream) {
   }
   const bool positions = ens->s[0].x != nullptr || ens->s[1].x != nullptr || ens->s[2].x != nullptr;
   for (int s = 0; s < 3; ++s) {
-    if (!species_ok(ens->s[s], s == 2, positions) || !fields_ok(ens->f[s], ens->s[s].count)) {
+    if (!species_ok(ens->s[s], s == 2, positions)) {
       set_error("invalid species " + std::to_string(s));
+      return QED_ERR_ARG;
+    }
+    if (!fields_ok(ens->f[s], ens->s[s].count)) {
+      set_error(fields_error(s));
       return QED_ERR_ARG;
     }
   }

@@ -904,6 +904,10 @@ __global__ void __launch_bounds__(kStepThreads, sizeof(T) == 4 ? kStepWavesPerSi
     n = hi > a.n_base ? hi - a.n_base : 0;
   }
   const int64_t num_tiles = (n + kMergedTile - 1) / kMergedTile;
+  if (num_tiles == 0) {  // an empty range: no events (the write kernel reads the list's length)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *const_cast<int64_t*>(a.list_len) = 0;
+    return;
+  }
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t dst0 = *a.dst_cursor, pair0 = *a.pair_cursor;
   int32_t any_event = 0;

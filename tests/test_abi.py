@@ -99,3 +99,35 @@ def test_merge_noalloc_limit_without_device(L):
     assert L.qed_merge_noalloc(C.byref(e), a, None) == 1
     assert b"limit" in L.qed_last_error()
     assert L.qed_merge_noalloc(None, None, None) == 1
+
+
+def test_short_fields_rejected_without_device(L):
+    """Per-particle fields (stride 1) must hold at least as many entries as
+    the species has particles; the step, the merged step, the validation pass
+    and qed_eval_particles refuse shorter ones before any HIP call (the
+    pointers below are never dereferenced)."""
+    import paper_2409_17299_amd as sf
+    fake = C.c_void_p(256)
+    e = sf.CEnsemble()
+    e.dtype = sf.F32
+    for s in range(3):
+        sp = e.s[s]
+        sp.px = sp.py = sp.pz = sp.w = sp.tau = sp.id = sp.alive = fake
+        sp.count, sp.capacity = 0, 1
+        e.f[s] = sf.CFields(*([fake] * 6), 0, 0)
+    e.s[2].count = e.s[2].capacity = 100
+    e.f[2] = sf.CFields(*([fake] * 6), 1, 99)
+    a = (sf.CAppend * 3)(*[sf.CAppend(fake, None, 0, 1) for _ in range(3)])
+    t = C.c_void_p(512)
+    cfg = sf.step_cfg()
+    st = sf.StepStats()
+    for fn in (L.qed_step, L.qed_step_merged):
+        assert fn(t, C.byref(cfg), C.byref(e), a, 1.0, 0, 0, C.byref(st), None) == 1
+        assert b"fields of species 2" in L.qed_last_error()
+    bad = (C.c_int64 * 3)()
+    assert L.qed_validate(C.byref(e), bad, None) == 1
+    assert b"fields of species 2" in L.qed_last_error()
+    f = sf.CFields(*([fake] * 6), 1, 99)
+    assert L.qed_eval_particles(t, 2, sf.F32, fake, fake, fake, C.byref(f), 100, fake, fake, None) == 1
+    f2 = sf.CFields(*([fake] * 6), 2, 1000)  # a stride other than 0 or 1
+    assert L.qed_eval_particles(t, 2, sf.F32, fake, fake, fake, C.byref(f2), 100, fake, fake, None) == 1

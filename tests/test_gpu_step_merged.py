@@ -109,6 +109,48 @@ def test_append_capacity():
     assert not app[2].data[5_000 * rec:].any()
 
 
+def test_rounds_that_append_no_photons():
+    """A round whose leptons emit nothing leaves the merged step an empty
+    appended-photon range, sized on the device.  Its photon pass must list
+    no events, whatever the previous launch (here the input photons' pass)
+    left in the event list.  A step with emission first fills the photon
+    append buffers; a step without emission (pairs on) then starts from
+    fresh copies of the input ensemble, its per-particle fields covering
+    every particle, on the same append buffers, which still hold those
+    photon records.  It must equal qed_step followed by qed_merge."""
+    torch, sf = need_gpu()
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 400), np.arange(0, 4_000_000, 400),
+                                                  np.arange(0, 2_000_000, 100)])
+    tabs = sf.Tables()
+    ma, fa, aa = build(sf, torch, wl, torch.float32)
+    mb, fb, ab = build(sf, torch, wl, torch.float32)
+    cfg = sf.step_cfg(push=False, gamma_min=2.0)
+    rc, st_a = sf.step(tabs, ma, fa, aa, wl.dt, 5, 0, cfg)
+    rc_b, st_b = sf.step_merged(tabs, mb, fb, ab, wl.dt, 5, 0, cfg)
+    torch.cuda.synchronize()
+    assert rc == 0 and rc_b == 0 and st_a.n_emit == st_b.n_emit > 100_000
+    # fresh input ensembles and fields (as many entries as particles); the append buffers are kept
+    ma, fa, _ = build(sf, torch, wl, torch.float32)
+    mb, fb, _ = build(sf, torch, wl, torch.float32)
+    cfg = sf.step_cfg(push=False, gamma_min=2.0, emission=False)
+    rc, st_a = sf.step(tabs, ma, fa, aa, wl.dt, 5, 1, cfg)
+    sf.merge(ma, fa, aa)
+    rc_b, st_b = sf.step_merged(tabs, mb, fb, ab, wl.dt, 5, 1, cfg)
+    torch.cuda.synchronize()
+    assert rc == 0 and rc_b == 0
+    print(f"without emission: {st_a.n_emit} photons, {st_a.n_pair} pairs, {st_a.n_rounds} rounds")
+    assert st_a.n_emit == st_b.n_emit == 0 and st_a.n_pair == st_b.n_pair > 0
+    assert st_a.n_rounds == st_b.n_rounds
+    for s in range(3):
+        assert ma[s].count == mb[s].count, (s, ma[s].count, mb[s].count)
+        A, B = arrays(ma[s]), arrays(mb[s])
+        for name in A:
+            assert np.array_equal(A[name], B[name]), (s, name)
+    for s in range(2):
+        assert aa[s].count == ab[s].count
+        assert np.array_equal(aa[s].records(), ab[s].records())
+
+
 def test_staged_records_equal_direct_stores(monkeypatch):
     """The FP32 lepton write kernel stages child records in LDS and writes them
     in half lines; with SFQED_WRITE_STAGING=0 it stores each record directly
