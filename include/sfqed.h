@@ -357,10 +357,12 @@ typedef struct {
 } qed_box;
 
 /* Per-particle field arrays written by qed_gather_fields (dtype of the
- * ensemble, capacity >= the species' count); pass them to qed_step as a
- * qed_fields with stride 1. */
+ * ensemble); n: entries per array, at least the species' count (else
+ * QED_ERR_ARG before any device work).  Pass them to qed_step as a
+ * qed_fields with stride 1 and the same n. */
 typedef struct {
   void *ex, *ey, *ez, *bx, *by, *bz;
+  int64_t n;
 } qed_field_arrays;
 
 /* For every particle of the three species of `ens` (positions required):

@@ -116,7 +116,7 @@ class CBox(C.Structure):
 
 
 class CFieldArrays(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")]
+    _fields_ = [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")] + [("n", C.c_int64)]
 
 
 _lib = None
@@ -579,7 +579,11 @@ def gather_fields(main: list, grid: Grid1d, box_: CBox, out: list, stream=None):
         if main[s].count > 0 and (out[s].stride != 1 or out[s].ex.numel() < main[s].count):
             raise SfqedError(1, f"gather_fields: output of species {s} holds fewer than {main[s].count} particles")
     e = _ensemble(main, out)
-    o = (CFieldArrays * 3)(*[CFieldArrays(*[_ptr(t) for t in (f.ex, f.ey, f.ez, f.bx, f.by, f.bz)]) for f in out])
+    def arrays(f):
+        ts = (f.ex, f.ey, f.ez, f.bx, f.by, f.bz)
+        return CFieldArrays(*[_ptr(t) for t in ts], min(t.numel() for t in ts))
+
+    o = (CFieldArrays * 3)(*[arrays(f) for f in out])
     g = grid.c()
     _check(lib().qed_gather_fields(C.byref(e), C.byref(g), C.byref(box_), o, _stream(stream)))
 

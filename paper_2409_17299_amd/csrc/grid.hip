@@ -265,6 +265,11 @@ qed_status qed_gather_fields(qed_ensemble* ens, const qed_grid1d* g, const qed_b
       set_error("gather_fields: species " + std::to_string(s) + " needs positions and six output arrays");
       return QED_ERR_ARG;
     }
+    if (o.n < sp.count) {
+      set_error("gather_fields: the output arrays of species " + std::to_string(s) + " hold fewer entries than " +
+                std::to_string(sp.count) + " particles");
+      return QED_ERR_ARG;
+    }
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (ens->dtype == QED_F32) return sfqed::gather_impl<float>(ens, *g, *box, out, st);

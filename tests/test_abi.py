@@ -131,3 +131,22 @@ def test_short_fields_rejected_without_device(L):
     assert L.qed_eval_particles(t, 2, sf.F32, fake, fake, fake, C.byref(f), 100, fake, fake, None) == 1
     f2 = sf.CFields(*([fake] * 6), 2, 1000)  # a stride other than 0 or 1
     assert L.qed_eval_particles(t, 2, sf.F32, fake, fake, fake, C.byref(f2), 100, fake, fake, None) == 1
+
+
+def test_short_gather_output_rejected_without_device(L):
+    """qed_gather_fields refuses output arrays with fewer entries than
+    particles before any HIP call (pointers never dereferenced)."""
+    import paper_2409_17299_amd as sf
+    fake = C.c_void_p(256)
+    e = sf.CEnsemble()
+    e.dtype = sf.F32
+    for s in range(3):
+        sp = e.s[s]
+        sp.px = sp.py = sp.pz = sp.w = sp.tau = sp.id = sp.alive = sp.x = sp.y = sp.z = fake
+        sp.count, sp.capacity = 0, 1
+    e.s[1].count = e.s[1].capacity = 10
+    g = sf.CGrid1d(sf.F32, 8, 0.0, 1.0, *([fake] * 6))
+    b = sf.box((0, 0, 0), (1.0, 1.0, 1.0))
+    out = (sf.CFieldArrays * 3)(*[sf.CFieldArrays(*([fake] * 6), 9) for _ in range(3)])
+    assert L.qed_gather_fields(C.byref(e), C.byref(g), C.byref(b), out, None) == 1
+    assert b"fewer entries" in L.qed_last_error()
