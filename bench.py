@@ -103,7 +103,11 @@ def pretouch_hbm(torch, margin_gib: int = 8) -> dict:
     after 10 warm-up steps), while any later process on the box, or the same
     process after this pass, runs the same steps in 43.6-44.8 ms; the
     compute-bound count pass is the same in both.  The allocations alone
-    make the difference (writing the blocks adds nothing)."""
+    make the difference (writing the blocks adds nothing).  After this pass
+    large allocations are slow (a cascade that grows its buffers inside its
+    timed steps stalls at every growth), so only the crossed-field step,
+    whose buffers are all allocated before its timed steps, uses it; the
+    bench line also reports that step timed before it."""
     t0 = time.perf_counter()
     free, _ = torch.cuda.mem_get_info()
     n = max(int((free - (margin_gib << 30)) // (1 << 30)), 0)
@@ -153,6 +157,28 @@ class DeviceWorkload:
             return rc, st
         self.sf.merge(self.main, self.fields, self.app)
         return 0, st
+
+
+def size_buffers(sf, torch, wl, tables, cfg, dtype, n: int, merged: bool) -> list:
+    """Append capacities for the workload: one generous step (grown until it
+    fits), then 1.25 times what it needed."""
+    caps = [int(n * 12), int(n * 12), int(min(n * 100, (1 << 30) - 1024))]
+    while True:
+        dw = DeviceWorkload(sf, torch, wl, caps, dtype)
+        rc, st = dw.step(tables, 10_000, cfg, merged=merged)
+        if rc == 0:
+            break
+        if rc != 2:
+            raise sf.SfqedError(rc, "sizing step")
+        need = list(st.required_capacity)
+        log(f"  append capacity {caps} too small (needed at least {need}); growing")
+        caps = [int(min(max(c * 2, r * 1.3), (1 << 30) - 1024)) for c, r in zip(caps, need)]
+        del dw
+        torch.cuda.empty_cache()
+    caps = [int(min(max(r * 1.25, 1024), (1 << 30) - 1024)) for r in st.required_capacity]
+    del dw
+    torch.cuda.empty_cache()
+    return caps
 
 
 def sum_stats(stats: list) -> dict:
@@ -612,7 +638,7 @@ def main(argv=None):
     ap.add_argument("--seeds", type=int, default=1_000_000, help="seed electrons of the rotating_e cascade")
     ap.add_argument("--gamma-min", type=float, default=2.0)
     ap.add_argument("--no-pretouch", action="store_true",
-                    help="skip allocating and freeing most of HBM before the workload (see pretouch_hbm)")
+                    help="crossed-field step: skip the first-allocation timing and the HBM pre-allocation (pretouch_hbm)")
     ap.add_argument("--per-particle", action="store_true",
                     help="only run the per-particle kernels of the precision sweep (chi, rate, one sample)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -631,7 +657,6 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    pretouch = None if args.no_pretouch or args.calibrate_copy else pretouch_hbm(torch)
     if args.workload == "rotating_e":
         print(json.dumps(cascade_bench(sf, torch, 20, args.seeds, merged=not args.two_call)), flush=True)
         return 0
@@ -664,25 +689,28 @@ def main(argv=None):
     # gaps); the same steps are then run again with them for the per-kernel times
     cfg_timed = sf.step_cfg(push=False, gamma_min=args.gamma_min, profile=False, nev=False)
 
-    # size the append buffers with one generous step
-    caps = [int(args.n * 12), int(args.n * 12), int(min(args.n * 100, (1 << 30) - 1024))]
-    while True:
+    merged = not args.two_call
+    caps = size_buffers(sf, torch, wl, tables, cfg, dtype, args.n, merged)
+    log(f"  capacities {caps}")
+    first_process = None
+    pretouch = None
+    if not args.no_pretouch:
+        # the same steps in this process's first allocation of HBM, then the
+        # pre-allocation (pretouch_hbm) and the measured run below
         dw = DeviceWorkload(sf, torch, wl, caps, dtype)
-        rc, st = dw.step(tables, 10_000, cfg, merged=not args.two_call)
-        if rc == 0:
-            break
-        if rc != 2:
-            raise sf.SfqedError(rc, "sizing step")
-        need = list(st.required_capacity)
-        log(f"  append capacity {caps} too small (needed at least {need}); growing")
-        caps = [int(min(max(c * 2, r * 1.3), (1 << 30) - 1024)) for c, r in zip(caps, need)]
+        for i in range(args.warmup):
+            assert dw.step(tables, i, cfg_timed, merged=merged)[0] == 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            assert dw.step(tables, args.warmup + i, cfg_timed, merged=merged)[0] == 0
+        torch.cuda.synchronize()
+        first_process = round((time.perf_counter() - t0) * 1e3 / args.steps, 3)
+        log(f"first allocation of HBM: {first_process} ms/step")
         del dw
         torch.cuda.empty_cache()
-    caps = [int(min(max(r * 1.25, 1024), (1 << 30) - 1024)) for r in st.required_capacity]
-    del dw
-    torch.cuda.empty_cache()
+        pretouch = pretouch_hbm(torch)
     dw = DeviceWorkload(sf, torch, wl, caps, dtype)
-    log(f"  capacities {caps}")
 
     for i in range(args.warmup):
         rc, st = dw.step(tables, i, cfg, merged=not args.two_call)
@@ -739,7 +767,7 @@ def main(argv=None):
                       "gamma_min": args.gamma_min, "precision": "fp32 particles/tables, fp64 optical depth",
                       "events_per_step": events, "rounds": S["n_rounds"] / args.steps,
                       "lepton_writes": {"from_event_log": S["log_replays"], "direct": S["log_reruns"]},
-                      "hbm_pretouch": pretouch},
+                      "hbm_pretouch": pretouch, "ms_per_step_first_allocation": first_process},
            "roofline": roof,
            "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                        for k, v in kern.items()}}
