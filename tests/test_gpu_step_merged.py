@@ -109,7 +109,8 @@ def test_append_capacity():
     assert not app[2].data[5_000 * rec:].any()
 
 
-def test_rounds_that_append_no_photons():
+@pytest.mark.parametrize("dtype_name", ["float32", "float64"])
+def test_rounds_that_append_no_photons(dtype_name):
     """A round whose leptons emit nothing leaves the merged step an empty
     appended-photon range, sized on the device.  Its photon pass must list
     no events, whatever the previous launch (here the input photons' pass)
@@ -122,16 +123,17 @@ def test_rounds_that_append_no_photons():
     wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 400), np.arange(0, 4_000_000, 400),
                                                   np.arange(0, 2_000_000, 100)])
     tabs = sf.Tables()
-    ma, fa, aa = build(sf, torch, wl, torch.float32)
-    mb, fb, ab = build(sf, torch, wl, torch.float32)
+    dtype = getattr(torch, dtype_name)
+    ma, fa, aa = build(sf, torch, wl, dtype)
+    mb, fb, ab = build(sf, torch, wl, dtype)
     cfg = sf.step_cfg(push=False, gamma_min=2.0)
     rc, st_a = sf.step(tabs, ma, fa, aa, wl.dt, 5, 0, cfg)
     rc_b, st_b = sf.step_merged(tabs, mb, fb, ab, wl.dt, 5, 0, cfg)
     torch.cuda.synchronize()
     assert rc == 0 and rc_b == 0 and st_a.n_emit == st_b.n_emit > 100_000
     # fresh input ensembles and fields (as many entries as particles); the append buffers are kept
-    ma, fa, _ = build(sf, torch, wl, torch.float32)
-    mb, fb, _ = build(sf, torch, wl, torch.float32)
+    ma, fa, _ = build(sf, torch, wl, dtype)
+    mb, fb, _ = build(sf, torch, wl, dtype)
     cfg = sf.step_cfg(push=False, gamma_min=2.0, emission=False)
     rc, st_a = sf.step(tabs, ma, fa, aa, wl.dt, 5, 1, cfg)
     sf.merge(ma, fa, aa)
@@ -242,3 +244,27 @@ def test_replayed_writes_with_push_and_positions(monkeypatch):
                                    steps=3, merged=True)
     print(f"3 merged steps with push and positions: counts {counts}, identical to the direct writes")
     assert counts[0] > wl.species[0].n
+
+
+def test_short_fields_are_refused_before_any_change():
+    """Per-particle fields with fewer entries than particles: both steps
+    return QED_ERR_ARG before any device work, and the ensemble and the
+    append buffers are left as they were."""
+    torch, sf = need_gpu()
+    wl = synth.crossed_field(10_000_000, indices=[np.arange(0, 4_000_000, 4000), np.arange(0, 4_000_000, 4000),
+                                                  np.arange(0, 2_000_000, 4000)])
+    main, fields, app = build(sf, torch, wl, torch.float32)
+    short = sf.Fields(*[getattr(fields[2], c)[:-1] for c in ("ex", "ey", "ez", "bx", "by", "bz")], stride=1)
+    before = [arrays(m) for m in main]
+    counts = [m.count for m in main]
+    for fn in (sf.step, sf.step_merged):
+        rc, _ = fn(sf.Tables(), main, [fields[0], fields[1], short], app, wl.dt, 0, 0,
+                   sf.step_cfg(push=False), check=False)
+        assert rc == 1
+        assert b"fields of species 2" in sf.lib().qed_last_error()
+    torch.cuda.synchronize()
+    assert [m.count for m in main] == counts and [a.count for a in app] == [0, 0, 0]
+    for s in range(3):
+        A = arrays(main[s])
+        for name in A:
+            assert np.array_equal(A[name], before[s][name]), (s, name)
